@@ -1,0 +1,903 @@
+/*
+ * FP64 CPU oracle for the FDTD-PIC time step of Liu, Zhao, Wang & Liu,
+ * "Numerical study of three-dimensional PIC for the surface plasmon
+ * excitation based on Drude model" (arXiv:1505.04007).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * definition that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg load it.  It shares no
+ * code, header or constant table with the GPU library.
+ *
+ * Everything is SI and double precision.  Each Yee component is stored with
+ * its own extents on the full staggered lattice (Sec. II, the index
+ * convention stated after Eq. 6):
+ *   Ex[nx][ny+1][nz+1] at (i+1/2, j, k)    Hx[nx+1][ny][nz] at (i, j+1/2, k+1/2)
+ *   Ey[nx+1][ny][nz+1] at (i, j+1/2, k)    Hy[nx][ny+1][nz] at (i+1/2, j, k+1/2)
+ *   Ez[nx+1][ny+1][nz] at (i, j, k+1/2)    Hz[nx][ny][nz+1] at (i+1/2, j+1/2, k)
+ * C order, k fastest.  On a periodic axis node n duplicates node 0 and is
+ * re-synchronised after every E update.
+ *
+ * One step n -> n+1 (Sec. II, text after Eq. 8: polarization current first,
+ * then E; magnetic field as in vacuum; particles through the Yee fields):
+ *   1. H^{n+1/2} = H^{n-1/2} - (dt/mu0) curl E^n                 (vacuum form)
+ *   2. particles: gather E^n, B^n = mu0 (H^{n-1/2} + H^{n+1/2}) / 2,
+ *      relativistic Boris push, move, Esirkepov deposit of J_b^{n+1/2}
+ *   3. J^{n+1/2} = ca J^{n-1/2} + cb E^n on every E edge           (Eq. 6)
+ *   4. E^{n+1} = E^n + (dt/eps0)(curl H^{n+1/2} - J^{n+1/2} - J_b^{n+1/2})
+ *                                                                  (Eq. 8)
+ *   5. probes: F_p(w) += dt Ez_p^{n+1} exp(-i w (n+1) dt)
+ * with ca = (2 - g dt)/(2 + g dt), cb = 2 dt eps0 wp^2/(2 + g dt) (Eq. 6).
+ * Readings where the paper is silent or garbled (E^n in Eq. 6, the lost
+ * minus sign of Eq. 8, beam current in Eq. 8, pusher/deposit scheme, CPML
+ * in place of the split-field PML, edge material rule) are the ones listed
+ * in the design notes; each is restated at the code that applies it.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_C 299792458.0
+#define OR_MU0 1.25663706212e-6
+#define OR_EPS0 (1.0 / (OR_MU0 * OR_C * OR_C))
+#define OR_ETA0 (OR_MU0 * OR_C)
+
+enum { OR_PEC = 0, OR_PERIODIC = 1, OR_CPML = 2 };
+
+typedef struct {
+    int n[3];
+    double *v;
+} ofield;
+
+#define AT(f, i, j, k) \
+    ((f).v[((size_t)(i) * (size_t)(f).n[1] + (size_t)(j)) * (size_t)(f).n[2] + (size_t)(k)])
+
+typedef struct {
+    int n[3];
+    int bc[3];
+    int npml;
+    double dx, dt;
+    ofield E[3], H[3], Hprev[3], J[3], P[3], Jb[3], ca[3], cb[3];
+    /* psiE[c][a]: CPML memory of E component c for its derivative along a */
+    ofield psiE[3][3], psiH[3][3];
+    /* CPML profile along each axis: E-type at nodes 0..n, H-type at i+1/2 */
+    double *bE[3], *cE[3], *kE[3], *bH[3], *cH[3], *kH[3];
+    unsigned char *lE[3], *lH[3];
+    /* particles */
+    long np;
+    double *x, *y, *z, *ux, *uy, *uz;
+    unsigned char *alive;
+    double q, m, w;
+    /* probes */
+    int nprobe, nfreq;
+    int *pijk;
+    double *omega, *fre, *fim;
+    long step;
+    double t_field, t_part;
+    long pushes;
+} osim;
+
+static ofield fnew(int a, int b, int c)
+{
+    ofield f;
+    f.n[0] = a;
+    f.n[1] = b;
+    f.n[2] = c;
+    f.v = (double *)calloc((size_t)a * b * c + 1, sizeof(double));
+    return f;
+}
+
+static void ffree(ofield *f)
+{
+    free(f->v);
+    f->v = NULL;
+}
+
+static size_t fsize(const ofield *f) { return (size_t)f->n[0] * f->n[1] * f->n[2]; }
+
+static double now_s(void)
+{
+    struct timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return (double)t.tv_sec + 1e-9 * (double)t.tv_nsec;
+}
+
+/* Extents of component c: staggered (n cells) along c for E and across c for H. */
+static void e_ext(const osim *s, int c, int e[3])
+{
+    for (int a = 0; a < 3; ++a) e[a] = s->n[a] + (a == c ? 0 : 1);
+}
+static void h_ext(const osim *s, int c, int e[3])
+{
+    for (int a = 0; a < 3; ++a) e[a] = s->n[a] + (a == c ? 1 : 0);
+}
+
+/*
+ * CPML grading (Roden & Gedney 2000; the absorbing layer that stands in for
+ * the Berenger PML of Sec. III).  Depth rho into a layer of thickness
+ * L = npml dx, sigma = sigma_max (rho/L)^m, kappa = 1 + (kappa_max-1)(rho/L)^m,
+ * alpha = alpha_max (1 - rho/L); b = exp(-(sigma/kappa + alpha) dt/eps0),
+ * c = sigma (b-1) / (sigma kappa + kappa^2 alpha).
+ */
+static void cpml_coeff(const osim *s, int a, double pos, const double *pml, double *b,
+                       double *c, double *kap, unsigned char *in)
+{
+    const double L = (double)s->npml;
+    double rho = 0.0;
+    if (pos < L) rho = L - pos;
+    if (pos > (double)s->n[a] - L) rho = pos - ((double)s->n[a] - L);
+    if (s->bc[a] != OR_CPML || s->npml <= 0 || rho <= 0.0) {
+        *b = 1.0;
+        *c = 0.0;
+        *kap = 1.0;
+        *in = 0;
+        return;
+    }
+    const double m = pml[0];
+    const double smax = pml[1] * 0.8 * (m + 1.0) / (OR_ETA0 * s->dx);
+    const double r = rho / L;
+    const double sig = smax * pow(r, m);
+    const double kap_ = 1.0 + (pml[2] - 1.0) * pow(r, m);
+    const double alp = pml[3] * (1.0 - r);
+    *b = exp(-(sig / kap_ + alp) * s->dt / OR_EPS0);
+    *c = (sig > 0.0) ? sig * (*b - 1.0) / (sig * kap_ + kap_ * kap_ * alp) : 0.0;
+    *kap = kap_;
+    *in = 1;
+}
+
+/* Drude coefficients of Eq. 6 (c.f. the printed fractions). */
+static void drude_coeff(double wp, double g, double dt, double *ca, double *cb)
+{
+    *ca = (2.0 - g * dt) / (2.0 + g * dt);
+    *cb = 2.0 * dt * OR_EPS0 * wp * wp / (2.0 + g * dt);
+}
+
+/* Map (nx,ny,nz), C order (k fastest). */
+static size_t cidx(const osim *s, int i, int j, int k)
+{
+    return ((size_t)i * s->n[1] + j) * s->n[2] + k;
+}
+
+static int clampi(int v, int hi) { return v < hi ? v : hi - 1; }
+
+osim *osim_create(int nx, int ny, int nz, const int *bc, int npml, const double *pml,
+                  double dx, double dt, const double *wp_map, const double *gamma_map)
+{
+    osim *s = (osim *)calloc(1, sizeof(osim));
+    s->n[0] = nx;
+    s->n[1] = ny;
+    s->n[2] = nz;
+    for (int a = 0; a < 3; ++a) s->bc[a] = bc[a];
+    s->npml = npml;
+    s->dx = dx;
+    s->dt = dt;
+    int e[3];
+    for (int c = 0; c < 3; ++c) {
+        e_ext(s, c, e);
+        s->E[c] = fnew(e[0], e[1], e[2]);
+        s->J[c] = fnew(e[0], e[1], e[2]);
+        s->P[c] = fnew(e[0], e[1], e[2]);
+        s->Jb[c] = fnew(e[0], e[1], e[2]);
+        s->ca[c] = fnew(e[0], e[1], e[2]);
+        s->cb[c] = fnew(e[0], e[1], e[2]);
+        for (int a = 0; a < 3; ++a) s->psiE[c][a] = (a != c && bc[a] == OR_CPML) ? fnew(e[0], e[1], e[2]) : (ofield){{0, 0, 0}, NULL};
+        h_ext(s, c, e);
+        s->H[c] = fnew(e[0], e[1], e[2]);
+        s->Hprev[c] = fnew(e[0], e[1], e[2]);
+        for (int a = 0; a < 3; ++a) s->psiH[c][a] = (a != c && bc[a] == OR_CPML) ? fnew(e[0], e[1], e[2]) : (ofield){{0, 0, 0}, NULL};
+    }
+    /*
+     * Edge material: cell (i,j,k) owns Ex(i+1/2,j,k), Ey(i,j+1/2,k),
+     * Ez(i,j,k+1/2); edges on the upper walls take the last cell.  wp = 0
+     * gives ca = 1, cb = 0 and J stays 0 in vacuum (Sec. II, after Eq. 8).
+     */
+    for (int c = 0; c < 3; ++c) {
+        e_ext(s, c, e);
+        for (int i = 0; i < e[0]; ++i)
+            for (int j = 0; j < e[1]; ++j)
+                for (int k = 0; k < e[2]; ++k) {
+                    size_t m = cidx(s, clampi(i, nx), clampi(j, ny), clampi(k, nz));
+                    drude_coeff(wp_map[m], gamma_map[m], dt, &AT(s->ca[c], i, j, k),
+                                &AT(s->cb[c], i, j, k));
+                }
+    }
+    for (int a = 0; a < 3; ++a) {
+        int n = s->n[a];
+        s->bE[a] = calloc(n + 1, sizeof(double));
+        s->cE[a] = calloc(n + 1, sizeof(double));
+        s->kE[a] = calloc(n + 1, sizeof(double));
+        s->lE[a] = calloc(n + 1, 1);
+        s->bH[a] = calloc(n, sizeof(double));
+        s->cH[a] = calloc(n, sizeof(double));
+        s->kH[a] = calloc(n, sizeof(double));
+        s->lH[a] = calloc(n, 1);
+        for (int i = 0; i <= n; ++i)
+            cpml_coeff(s, a, (double)i, pml, &s->bE[a][i], &s->cE[a][i], &s->kE[a][i], &s->lE[a][i]);
+        for (int i = 0; i < n; ++i)
+            cpml_coeff(s, a, i + 0.5, pml, &s->bH[a][i], &s->cH[a][i], &s->kH[a][i], &s->lH[a][i]);
+    }
+    return s;
+}
+
+void osim_destroy(osim *s)
+{
+    if (!s) return;
+    for (int c = 0; c < 3; ++c) {
+        ffree(&s->E[c]);
+        ffree(&s->H[c]);
+        ffree(&s->Hprev[c]);
+        ffree(&s->J[c]);
+        ffree(&s->P[c]);
+        ffree(&s->Jb[c]);
+        ffree(&s->ca[c]);
+        ffree(&s->cb[c]);
+        for (int a = 0; a < 3; ++a) {
+            free(s->psiE[c][a].v);
+            free(s->psiH[c][a].v);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        free(s->bE[a]);
+        free(s->cE[a]);
+        free(s->kE[a]);
+        free(s->lE[a]);
+        free(s->bH[a]);
+        free(s->cH[a]);
+        free(s->kH[a]);
+        free(s->lH[a]);
+    }
+    free(s->x);
+    free(s->y);
+    free(s->z);
+    free(s->ux);
+    free(s->uy);
+    free(s->uz);
+    free(s->alive);
+    free(s->pijk);
+    free(s->omega);
+    free(s->fre);
+    free(s->fim);
+    free(s);
+}
+
+/* Raw state access: which 0=E 1=H 2=J_pol 3=P 4=J_b 5=H^{n-1/2} copy. */
+double *osim_field_ptr(osim *s, int which, int comp, int *ext)
+{
+    ofield *f = NULL;
+    switch (which) {
+    case 0: f = &s->E[comp]; break;
+    case 1: f = &s->H[comp]; break;
+    case 2: f = &s->J[comp]; break;
+    case 3: f = &s->P[comp]; break;
+    case 4: f = &s->Jb[comp]; break;
+    case 5: f = &s->Hprev[comp]; break;
+    default: return NULL;
+    }
+    for (int a = 0; a < 3; ++a) ext[a] = f->n[a];
+    return f->v;
+}
+
+/* Index of node/half-position `i` along axis a, folded for periodic axes. */
+static int wrap(const osim *s, int a, int i)
+{
+    int n = s->n[a];
+    return ((i % n) + n) % n;
+}
+
+/*
+ * A tangential E edge on a PEC wall (also behind a CPML) is never updated;
+ * on a periodic axis node n is the copy of node 0.
+ */
+static int e_node_updated(const osim *s, int a, int i)
+{
+    if (s->bc[a] == OR_PERIODIC) return i < s->n[a];
+    return i > 0 && i < s->n[a];
+}
+
+/* ---- step 1: H in vacuum form, with CPML stretching in layer cells ---- */
+static void update_H(osim *s)
+{
+    const double ch = s->dt / (OR_MU0 * s->dx);
+    ofield Ex = s->E[0], Ey = s->E[1], Ez = s->E[2];
+    for (int c = 0; c < 3; ++c) memcpy(s->Hprev[c].v, s->H[c].v, fsize(&s->H[c]) * sizeof(double));
+
+    /* Hx(i, j+1/2, k+1/2) -= (dt/mu0) (dEz/dy - dEy/dz) */
+    ofield Hx = s->H[0];
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < Hx.n[0]; ++i)
+        for (int j = 0; j < Hx.n[1]; ++j)
+            for (int k = 0; k < Hx.n[2]; ++k) {
+                double dy = AT(Ez, i, j + 1, k) - AT(Ez, i, j, k);
+                double dz = AT(Ey, i, j, k + 1) - AT(Ey, i, j, k);
+                if (s->lH[1][j]) {
+                    double *p = &AT(s->psiH[0][1], i, j, k);
+                    *p = s->bH[1][j] * *p + s->cH[1][j] * dy;
+                    dy = dy / s->kH[1][j] + *p;
+                }
+                if (s->lH[2][k]) {
+                    double *p = &AT(s->psiH[0][2], i, j, k);
+                    *p = s->bH[2][k] * *p + s->cH[2][k] * dz;
+                    dz = dz / s->kH[2][k] + *p;
+                }
+                AT(Hx, i, j, k) -= ch * (dy - dz);
+            }
+    /* Hy(i+1/2, j, k+1/2) -= (dt/mu0) (dEx/dz - dEz/dx) */
+    ofield Hy = s->H[1];
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < Hy.n[0]; ++i)
+        for (int j = 0; j < Hy.n[1]; ++j)
+            for (int k = 0; k < Hy.n[2]; ++k) {
+                double dz = AT(Ex, i, j, k + 1) - AT(Ex, i, j, k);
+                double dx = AT(Ez, i + 1, j, k) - AT(Ez, i, j, k);
+                if (s->lH[2][k]) {
+                    double *p = &AT(s->psiH[1][2], i, j, k);
+                    *p = s->bH[2][k] * *p + s->cH[2][k] * dz;
+                    dz = dz / s->kH[2][k] + *p;
+                }
+                if (s->lH[0][i]) {
+                    double *p = &AT(s->psiH[1][0], i, j, k);
+                    *p = s->bH[0][i] * *p + s->cH[0][i] * dx;
+                    dx = dx / s->kH[0][i] + *p;
+                }
+                AT(Hy, i, j, k) -= ch * (dz - dx);
+            }
+    /* Hz(i+1/2, j+1/2, k) -= (dt/mu0) (dEy/dx - dEx/dy) */
+    ofield Hz = s->H[2];
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < Hz.n[0]; ++i)
+        for (int j = 0; j < Hz.n[1]; ++j)
+            for (int k = 0; k < Hz.n[2]; ++k) {
+                double dx = AT(Ey, i + 1, j, k) - AT(Ey, i, j, k);
+                double dy = AT(Ex, i, j + 1, k) - AT(Ex, i, j, k);
+                if (s->lH[0][i]) {
+                    double *p = &AT(s->psiH[2][0], i, j, k);
+                    *p = s->bH[0][i] * *p + s->cH[0][i] * dx;
+                    dx = dx / s->kH[0][i] + *p;
+                }
+                if (s->lH[1][j]) {
+                    double *p = &AT(s->psiH[2][1], i, j, k);
+                    *p = s->bH[1][j] * *p + s->cH[1][j] * dy;
+                    dy = dy / s->kH[1][j] + *p;
+                }
+                AT(Hz, i, j, k) -= ch * (dx - dy);
+            }
+}
+
+/* ---- steps 3+4: Eq. 6 then Eq. 8 on every updated E edge ---- */
+static void update_E(osim *s)
+{
+    const double ce = s->dt / (OR_EPS0 * s->dx);
+    const double cj = s->dt / OR_EPS0;
+    const double dt = s->dt;
+    ofield Hx = s->H[0], Hy = s->H[1], Hz = s->H[2];
+
+    /* Ex(i+1/2, j, k) += (dt/eps0) (dHz/dy - dHy/dz - J - Jb) */
+    ofield Ex = s->E[0];
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < Ex.n[0]; ++i)
+        for (int j = 0; j < Ex.n[1]; ++j)
+            for (int k = 0; k < Ex.n[2]; ++k) {
+                if (!e_node_updated(s, 1, j) || !e_node_updated(s, 2, k)) continue;
+                int jm = wrap(s, 1, j - 1), km = wrap(s, 2, k - 1);
+                double dy = AT(Hz, i, j, k) - AT(Hz, i, jm, k);
+                double dz = AT(Hy, i, j, k) - AT(Hy, i, j, km);
+                if (s->lE[1][j]) {
+                    double *p = &AT(s->psiE[0][1], i, j, k);
+                    *p = s->bE[1][j] * *p + s->cE[1][j] * dy;
+                    dy = dy / s->kE[1][j] + *p;
+                }
+                if (s->lE[2][k]) {
+                    double *p = &AT(s->psiE[0][2], i, j, k);
+                    *p = s->bE[2][k] * *p + s->cE[2][k] * dz;
+                    dz = dz / s->kE[2][k] + *p;
+                }
+                double jn = AT(s->ca[0], i, j, k) * AT(s->J[0], i, j, k) + AT(s->cb[0], i, j, k) * AT(Ex, i, j, k);
+                AT(s->J[0], i, j, k) = jn;
+                AT(s->P[0], i, j, k) += dt * jn;
+                AT(Ex, i, j, k) += ce * (dy - dz) - cj * (jn + AT(s->Jb[0], i, j, k));
+            }
+    /* Ey(i, j+1/2, k) += (dt/eps0) (dHx/dz - dHz/dx - J - Jb) */
+    ofield Ey = s->E[1];
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < Ey.n[0]; ++i)
+        for (int j = 0; j < Ey.n[1]; ++j)
+            for (int k = 0; k < Ey.n[2]; ++k) {
+                if (!e_node_updated(s, 0, i) || !e_node_updated(s, 2, k)) continue;
+                int im = wrap(s, 0, i - 1), km = wrap(s, 2, k - 1);
+                double dz = AT(Hx, i, j, k) - AT(Hx, i, j, km);
+                double dx = AT(Hz, i, j, k) - AT(Hz, im, j, k);
+                if (s->lE[2][k]) {
+                    double *p = &AT(s->psiE[1][2], i, j, k);
+                    *p = s->bE[2][k] * *p + s->cE[2][k] * dz;
+                    dz = dz / s->kE[2][k] + *p;
+                }
+                if (s->lE[0][i]) {
+                    double *p = &AT(s->psiE[1][0], i, j, k);
+                    *p = s->bE[0][i] * *p + s->cE[0][i] * dx;
+                    dx = dx / s->kE[0][i] + *p;
+                }
+                double jn = AT(s->ca[1], i, j, k) * AT(s->J[1], i, j, k) + AT(s->cb[1], i, j, k) * AT(Ey, i, j, k);
+                AT(s->J[1], i, j, k) = jn;
+                AT(s->P[1], i, j, k) += dt * jn;
+                AT(Ey, i, j, k) += ce * (dz - dx) - cj * (jn + AT(s->Jb[1], i, j, k));
+            }
+    /* Ez(i, j, k+1/2) += (dt/eps0) (dHy/dx - dHx/dy - J - Jb) */
+    ofield Ez = s->E[2];
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < Ez.n[0]; ++i)
+        for (int j = 0; j < Ez.n[1]; ++j)
+            for (int k = 0; k < Ez.n[2]; ++k) {
+                if (!e_node_updated(s, 0, i) || !e_node_updated(s, 1, j)) continue;
+                int im = wrap(s, 0, i - 1), jm = wrap(s, 1, j - 1);
+                double dx = AT(Hy, i, j, k) - AT(Hy, im, j, k);
+                double dy = AT(Hx, i, j, k) - AT(Hx, i, jm, k);
+                if (s->lE[0][i]) {
+                    double *p = &AT(s->psiE[2][0], i, j, k);
+                    *p = s->bE[0][i] * *p + s->cE[0][i] * dx;
+                    dx = dx / s->kE[0][i] + *p;
+                }
+                if (s->lE[1][j]) {
+                    double *p = &AT(s->psiE[2][1], i, j, k);
+                    *p = s->bE[1][j] * *p + s->cE[1][j] * dy;
+                    dy = dy / s->kE[1][j] + *p;
+                }
+                double jn = AT(s->ca[2], i, j, k) * AT(s->J[2], i, j, k) + AT(s->cb[2], i, j, k) * AT(Ez, i, j, k);
+                AT(s->J[2], i, j, k) = jn;
+                AT(s->P[2], i, j, k) += dt * jn;
+                AT(Ez, i, j, k) += ce * (dx - dy) - cj * (jn + AT(s->Jb[2], i, j, k));
+            }
+    /* Periodic copies: node n of a non-staggered periodic axis mirrors node 0. */
+    for (int c = 0; c < 3; ++c) {
+        ofield f = s->E[c];
+        for (int a = 0; a < 3; ++a) {
+            if (a == c || s->bc[a] != OR_PERIODIC) continue;
+            int n = s->n[a];
+            for (int i = 0; i < f.n[0]; ++i)
+                for (int j = 0; j < f.n[1]; ++j)
+                    for (int k = 0; k < f.n[2]; ++k) {
+                        int id[3] = {i, j, k};
+                        if (id[a] != n) continue;
+                        id[a] = 0;
+                        AT(f, i, j, k) = AT(f, id[0], id[1], id[2]);
+                    }
+        }
+        memset(s->Jb[c].v, 0, fsize(&s->Jb[c]) * sizeof(double));
+    }
+}
+
+/* ---- particles ---- */
+
+/* Value of a stored component at integer lattice index, 0 outside the box. */
+static double fetch(const osim *s, const ofield *f, int i, int j, int k)
+{
+    int id[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+        if (s->bc[a] == OR_PERIODIC) {
+            id[a] = wrap(s, a, id[a]);
+        } else if (id[a] < 0 || id[a] >= f->n[a]) {
+            return 0.0;
+        }
+    }
+    return AT(*f, id[0], id[1], id[2]);
+}
+
+/*
+ * Trilinear (cloud-in-cell) interpolation of one component on its own
+ * staggered lattice; off[a] = 1/2 on the axes where it sits at half cells.
+ * X is in cell units.
+ */
+static double interp(const osim *s, const ofield *f, const double off[3], const double X[3])
+{
+    int i0[3];
+    double fr[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = X[a] - off[a];
+        i0[a] = (int)floor(t);
+        fr[a] = t - i0[a];
+    }
+    double v = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                double wgt = (a ? fr[0] : 1.0 - fr[0]) * (b ? fr[1] : 1.0 - fr[1]) * (c ? fr[2] : 1.0 - fr[2]);
+                v += wgt * fetch(s, f, i0[0] + a, i0[1] + b, i0[2] + c);
+            }
+    return v;
+}
+
+/* E^n and B^n = mu0 (H^{n-1/2} + H^{n+1/2})/2 at a point given in metres. */
+void osim_gather(const osim *s, const double *pos, double *E, double *B)
+{
+    double X[3] = {pos[0] / s->dx, pos[1] / s->dx, pos[2] / s->dx};
+    for (int c = 0; c < 3; ++c) {
+        double oe[3] = {0, 0, 0}, oh[3] = {0.5, 0.5, 0.5};
+        oe[c] = 0.5;
+        oh[c] = 0.0;
+        E[c] = interp(s, &s->E[c], oe, X);
+        B[c] = OR_MU0 * 0.5 * (interp(s, &s->Hprev[c], oh, X) + interp(s, &s->H[c], oh, X));
+    }
+}
+
+/*
+ * Relativistic Boris rotation (Boris 1970; Birdsall & Langdon Sec. 15-4).
+ * u = gamma v in m/s, advanced from n-1/2 to n+1/2 under E, B at time n.
+ */
+void oracle_boris(double q, double m, double dt, const double *E, const double *B, double *u)
+{
+    const double h = q * dt / (2.0 * m);
+    double um[3], t[3], sv[3], up[3], uq[3];
+    for (int a = 0; a < 3; ++a) um[a] = u[a] + h * E[a];
+    double g = sqrt(1.0 + (um[0] * um[0] + um[1] * um[1] + um[2] * um[2]) / (OR_C * OR_C));
+    for (int a = 0; a < 3; ++a) t[a] = h * B[a] / g;
+    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    for (int a = 0; a < 3; ++a) sv[a] = 2.0 * t[a] / (1.0 + t2);
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    uq[0] = um[0] + (up[1] * sv[2] - up[2] * sv[1]);
+    uq[1] = um[1] + (up[2] * sv[0] - up[0] * sv[2]);
+    uq[2] = um[2] + (up[0] * sv[1] - up[1] * sv[0]);
+    for (int a = 0; a < 3; ++a) u[a] = uq[a] + h * E[a];
+}
+
+static double shape1(double t)
+{
+    double a = fabs(t);
+    return a < 1.0 ? 1.0 - a : 0.0;
+}
+
+static void add_at(osim *s, ofield *f, int i, int j, int k, double v)
+{
+    int id[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+        if (s->bc[a] == OR_PERIODIC) id[a] = wrap(s, a, id[a]);
+        else if (id[a] < 0 || id[a] >= f->n[a]) return;
+    }
+    AT(*f, id[0], id[1], id[2]) += v;
+}
+
+/*
+ * Charge-conserving deposit of one macro-particle moving X0 -> X1 (cell
+ * units), Esirkepov, Comput. Phys. Commun. 135 (2001) 144, first-order
+ * shape S(t) = max(0, 1-|t|) at the nodes.  Over a 4-node window per axis
+ * starting one node below the start cell:
+ *   Wx = dSx (S0y S0z + dSy S0z/2 + S0y dSz/2 + dSy dSz/3)   (and cyclic),
+ *   Jx(i+1/2) = -(q w / (dt dx^2)) sum_{i' <= i} Wx(i')      (and cyclic).
+ */
+static void deposit(osim *s, const double *X0, const double *X1, double qw)
+{
+    int base[3];
+    double S0[3][4], S1[3][4], dS[3][4];
+    for (int a = 0; a < 3; ++a) {
+        base[a] = (int)floor(X0[a]) - 1;
+        for (int m = 0; m < 4; ++m) {
+            S0[a][m] = shape1(X0[a] - (base[a] + m));
+            S1[a][m] = shape1(X1[a] - (base[a] + m));
+            dS[a][m] = S1[a][m] - S0[a][m];
+        }
+    }
+    const double f = -qw / (s->dt * s->dx * s->dx);
+    for (int b = 0; b < 4; ++b)
+        for (int c = 0; c < 4; ++c) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m) {
+                acc += dS[0][m] * (S0[1][b] * S0[2][c] + 0.5 * dS[1][b] * S0[2][c] +
+                                   0.5 * S0[1][b] * dS[2][c] + dS[1][b] * dS[2][c] / 3.0);
+                add_at(s, &s->Jb[0], base[0] + m, base[1] + b, base[2] + c, f * acc);
+            }
+        }
+    for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m) {
+                acc += dS[1][m] * (S0[0][a] * S0[2][c] + 0.5 * dS[0][a] * S0[2][c] +
+                                   0.5 * S0[0][a] * dS[2][c] + dS[0][a] * dS[2][c] / 3.0);
+                add_at(s, &s->Jb[1], base[0] + a, base[1] + m, base[2] + c, f * acc);
+            }
+        }
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m) {
+                acc += dS[2][m] * (S0[0][a] * S0[1][b] + 0.5 * dS[0][a] * S0[1][b] +
+                                   0.5 * S0[0][a] * dS[1][b] + dS[0][a] * dS[1][b] / 3.0);
+                add_at(s, &s->Jb[2], base[0] + a, base[1] + b, base[2] + m, f * acc);
+            }
+        }
+}
+
+/* Deposit one move given in metres into J_b with the configured q w. */
+void osim_deposit_move(osim *s, const double *p0, const double *p1)
+{
+    double X0[3], X1[3];
+    for (int a = 0; a < 3; ++a) {
+        X0[a] = p0[a] / s->dx;
+        X1[a] = p1[a] / s->dx;
+    }
+    deposit(s, X0, X1, s->q * s->w);
+}
+
+/*
+ * Step 2: gather, push, move, deposit.  A particle whose new position leaves
+ * [0, n dx) on a non-periodic axis is deactivated and its last move is not
+ * deposited; on a periodic axis it is folded back after the deposit.
+ */
+static void push_particles(osim *s)
+{
+    const double dx = s->dx;
+    for (long p = 0; p < s->np; ++p) {
+        if (!s->alive[p]) continue;
+        double pos[3] = {s->x[p], s->y[p], s->z[p]};
+        double E[3], B[3], u[3] = {s->ux[p], s->uy[p], s->uz[p]};
+        osim_gather(s, pos, E, B);
+        oracle_boris(s->q, s->m, s->dt, E, B, u);
+        double g = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / (OR_C * OR_C));
+        double X0[3], X1[3];
+        int out = 0;
+        for (int a = 0; a < 3; ++a) {
+            X0[a] = pos[a] / dx;
+            X1[a] = (pos[a] + s->dt * u[a] / g) / dx;
+            if (s->bc[a] != OR_PERIODIC && (X1[a] < 0.0 || X1[a] >= (double)s->n[a])) out = 1;
+        }
+        s->ux[p] = u[0];
+        s->uy[p] = u[1];
+        s->uz[p] = u[2];
+        if (out) {
+            s->alive[p] = 0;
+            continue;
+        }
+        deposit(s, X0, X1, s->q * s->w);
+        s->pushes++;
+        for (int a = 0; a < 3; ++a) {
+            if (s->bc[a] == OR_PERIODIC) {
+                double L = (double)s->n[a];
+                X1[a] = fmod(X1[a], L);
+                if (X1[a] < 0.0) X1[a] += L;
+            }
+        }
+        s->x[p] = X1[0] * dx;
+        s->y[p] = X1[1] * dx;
+        s->z[p] = X1[2] * dx;
+    }
+}
+
+void osim_set_particles(osim *s, long n, const double *x, const double *y, const double *z,
+                        const double *ux, const double *uy, const double *uz, double q, double m,
+                        double w)
+{
+    free(s->x);
+    free(s->y);
+    free(s->z);
+    free(s->ux);
+    free(s->uy);
+    free(s->uz);
+    free(s->alive);
+    s->np = n;
+    size_t b = (size_t)(n > 0 ? n : 1) * sizeof(double);
+    s->x = malloc(b);
+    s->y = malloc(b);
+    s->z = malloc(b);
+    s->ux = malloc(b);
+    s->uy = malloc(b);
+    s->uz = malloc(b);
+    s->alive = malloc(n > 0 ? n : 1);
+    for (long p = 0; p < n; ++p) {
+        s->x[p] = x[p];
+        s->y[p] = y[p];
+        s->z[p] = z[p];
+        s->ux[p] = ux[p];
+        s->uy[p] = uy[p];
+        s->uz[p] = uz[p];
+        s->alive[p] = 1;
+    }
+    s->q = q;
+    s->m = m;
+    s->w = w;
+}
+
+/* which: 0..5 = x y z ux uy uz (copy out); alive flags as 0/1 doubles for 6. */
+void osim_get_particles(const osim *s, int which, double *out)
+{
+    const double *src[6] = {s->x, s->y, s->z, s->ux, s->uy, s->uz};
+    for (long p = 0; p < s->np; ++p) out[p] = which < 6 ? src[which][p] : (double)s->alive[p];
+}
+
+/*
+ * Probes sample the nearest Ez node (i, j, k+1/2): i, j round half up,
+ * k = floor(z/dx) (ties toward +z).
+ */
+void osim_set_probes(osim *s, int nprobe, const double *xyz, int nfreq, const double *omega)
+{
+    free(s->pijk);
+    free(s->omega);
+    free(s->fre);
+    free(s->fim);
+    s->nprobe = nprobe;
+    s->nfreq = nfreq;
+    s->pijk = calloc(3 * (size_t)(nprobe > 0 ? nprobe : 1), sizeof(int));
+    s->omega = calloc((size_t)(nfreq > 0 ? nfreq : 1), sizeof(double));
+    s->fre = calloc((size_t)(nprobe * nfreq > 0 ? nprobe * nfreq : 1), sizeof(double));
+    s->fim = calloc((size_t)(nprobe * nfreq > 0 ? nprobe * nfreq : 1), sizeof(double));
+    for (int p = 0; p < nprobe; ++p) {
+        s->pijk[3 * p + 0] = (int)floor(xyz[3 * p + 0] / s->dx + 0.5);
+        s->pijk[3 * p + 1] = (int)floor(xyz[3 * p + 1] / s->dx + 0.5);
+        s->pijk[3 * p + 2] = (int)floor(xyz[3 * p + 2] / s->dx);
+    }
+    for (int f = 0; f < nfreq; ++f) s->omega[f] = omega[f];
+}
+
+static void sample_probes(osim *s)
+{
+    const double t = (double)s->step * s->dt; /* time of E^{n+1}, step already advanced */
+    for (int p = 0; p < s->nprobe; ++p) {
+        double ez = AT(s->E[2], s->pijk[3 * p], s->pijk[3 * p + 1], s->pijk[3 * p + 2]);
+        for (int f = 0; f < s->nfreq; ++f) {
+            double th = s->omega[f] * t;
+            s->fre[p * s->nfreq + f] += s->dt * ez * cos(th);
+            s->fim[p * s->nfreq + f] -= s->dt * ez * sin(th);
+        }
+    }
+}
+
+void osim_probe(const osim *s, double *re, double *im)
+{
+    for (int i = 0; i < s->nprobe * s->nfreq; ++i) {
+        re[i] = s->fre[i];
+        im[i] = s->fim[i];
+    }
+}
+
+/* Probe Ez values of the current E (for time series). */
+void osim_probe_values(const osim *s, double *out)
+{
+    for (int p = 0; p < s->nprobe; ++p)
+        out[p] = AT(s->E[2], s->pijk[3 * p], s->pijk[3 * p + 1], s->pijk[3 * p + 2]);
+}
+
+void osim_step(osim *s, long nsteps)
+{
+    for (long it = 0; it < nsteps; ++it) {
+        double t0 = now_s();
+        update_H(s);
+        double t1 = now_s();
+        push_particles(s);
+        double t2 = now_s();
+        update_E(s);
+        s->step++;
+        sample_probes(s);
+        double t3 = now_s();
+        s->t_field += (t1 - t0) + (t3 - t2);
+        s->t_part += t2 - t1;
+    }
+}
+
+long osim_get_step(const osim *s) { return s->step; }
+
+/* out[0] field seconds, out[1] particle seconds, out[2] pushes, out[3] threads */
+void osim_timing(const osim *s, double *out)
+{
+    out[0] = s->t_field;
+    out[1] = s->t_part;
+    out[2] = (double)s->pushes;
+#ifdef _OPENMP
+    out[3] = (double)omp_get_max_threads();
+#else
+    out[3] = 1.0;
+#endif
+}
+
+/* ---- diagnostics ---- */
+
+/* Node-centred CIC charge density rho on the (nx+1)(ny+1)(nz+1) nodes. */
+void osim_rho(const osim *s, double *rho)
+{
+    const int n1 = s->n[1] + 1, n2 = s->n[2] + 1;
+    memset(rho, 0, sizeof(double) * (size_t)(s->n[0] + 1) * n1 * n2);
+    const double v = s->dx * s->dx * s->dx;
+    for (long p = 0; p < s->np; ++p) {
+        if (!s->alive[p]) continue;
+        double X[3] = {s->x[p] / s->dx, s->y[p] / s->dx, s->z[p] / s->dx};
+        int i0[3];
+        double fr[3];
+        for (int a = 0; a < 3; ++a) {
+            i0[a] = (int)floor(X[a]);
+            fr[a] = X[a] - i0[a];
+        }
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    int id[3] = {i0[0] + a, i0[1] + b, i0[2] + c};
+                    int skip = 0;
+                    for (int d = 0; d < 3; ++d) {
+                        if (s->bc[d] == OR_PERIODIC) id[d] = wrap(s, d, id[d]);
+                        else if (id[d] < 0 || id[d] > s->n[d]) skip = 1;
+                    }
+                    if (skip) continue;
+                    double wgt = (a ? fr[0] : 1 - fr[0]) * (b ? fr[1] : 1 - fr[1]) * (c ? fr[2] : 1 - fr[2]);
+                    rho[((size_t)id[0] * n1 + id[1]) * n2 + id[2]] += s->q * s->w * wgt / v;
+                }
+    }
+}
+
+/*
+ * Gauss-law residual G = eps0 div E + div P - rho at interior nodes
+ * (1..n-1 on every axis; 0 elsewhere), with P^{n+1} = P^n + dt J^{n+1/2}
+ * the polarization of Eq. 2 accumulated from the Drude current.
+ */
+void osim_gauss(const osim *s, double *G)
+{
+    const int n0 = s->n[0] + 1, n1 = s->n[1] + 1, n2 = s->n[2] + 1;
+    double *rho = malloc(sizeof(double) * (size_t)n0 * n1 * n2);
+    osim_rho(s, rho);
+    memset(G, 0, sizeof(double) * (size_t)n0 * n1 * n2);
+    for (int i = 1; i < s->n[0]; ++i)
+        for (int j = 1; j < s->n[1]; ++j)
+            for (int k = 1; k < s->n[2]; ++k) {
+                double dE = (AT(s->E[0], i, j, k) - AT(s->E[0], i - 1, j, k)) +
+                            (AT(s->E[1], i, j, k) - AT(s->E[1], i, j - 1, k)) +
+                            (AT(s->E[2], i, j, k) - AT(s->E[2], i, j, k - 1));
+                double dP = (AT(s->P[0], i, j, k) - AT(s->P[0], i - 1, j, k)) +
+                            (AT(s->P[1], i, j, k) - AT(s->P[1], i, j - 1, k)) +
+                            (AT(s->P[2], i, j, k) - AT(s->P[2], i, j, k - 1));
+                size_t m = ((size_t)i * n1 + j) * n2 + k;
+                G[m] = (OR_EPS0 * dE + dP) / s->dx - rho[m];
+            }
+    free(rho);
+}
+
+/*
+ * Field energy (eps0 |E|^2 + mu0 |H|^2)/2 dx^3 summed over stored edges and
+ * faces (periodic copies at node n excluded), and bunch moments over the
+ * live particles: out = [energy, count, <x>,<y>,<z>, sx,sy,sz, <ux>,<uy>,<uz>].
+ */
+void osim_diag(const osim *s, double *out)
+{
+    double en = 0.0;
+    for (int which = 0; which < 2; ++which)
+        for (int c = 0; c < 3; ++c) {
+            const ofield *f = which ? &s->H[c] : &s->E[c];
+            const double coef = which ? OR_MU0 : OR_EPS0;
+            for (int i = 0; i < f->n[0]; ++i)
+                for (int j = 0; j < f->n[1]; ++j)
+                    for (int k = 0; k < f->n[2]; ++k) {
+                        int id[3] = {i, j, k};
+                        int dup = 0;
+                        for (int a = 0; a < 3; ++a)
+                            if (s->bc[a] == OR_PERIODIC && id[a] == s->n[a]) dup = 1;
+                        if (dup) continue;
+                        double v = AT(*f, i, j, k);
+                        en += 0.5 * coef * v * v;
+                    }
+        }
+    out[0] = en * s->dx * s->dx * s->dx;
+    double cnt = 0, mx[3] = {0, 0, 0}, m2[3] = {0, 0, 0}, mu[3] = {0, 0, 0};
+    for (long p = 0; p < s->np; ++p) {
+        if (!s->alive[p]) continue;
+        double v[3] = {s->x[p], s->y[p], s->z[p]}, u[3] = {s->ux[p], s->uy[p], s->uz[p]};
+        cnt += 1;
+        for (int a = 0; a < 3; ++a) {
+            mx[a] += v[a];
+            m2[a] += v[a] * v[a];
+            mu[a] += u[a];
+        }
+    }
+    out[1] = cnt;
+    for (int a = 0; a < 3; ++a) {
+        double mean = cnt > 0 ? mx[a] / cnt : 0.0;
+        double var = cnt > 0 ? m2[a] / cnt - mean * mean : 0.0;
+        out[2 + a] = mean;
+        out[5 + a] = var > 0 ? sqrt(var) : 0.0;
+        out[8 + a] = cnt > 0 ? mu[a] / cnt : 0.0;
+    }
+}
+
+/* Physical constants the oracle uses: c, mu0, eps0. */
+void oracle_constants(double *out)
+{
+    out[0] = OR_C;
+    out[1] = OR_MU0;
+    out[2] = OR_EPS0;
+}

@@ -1,0 +1,210 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) FDTD-PIC library.
+ *
+ * The library advances the particle-in-cell model of Liu, Zhao, Wang & Liu,
+ * "Numerical study of three-dimensional PIC for the surface plasmon
+ * excitation based on Drude model" (arXiv:1505.04007):
+ *
+ *   - Yee leapfrog curl updates of E and H (Sec. II, Eqs. 7-8; the magnetic
+ *     update "as in vacuum", text after Eq. 8),
+ *   - the Drude polarization current J of Eq. 5, discretised as Eq. 6 with
+ *     ca = (2 - g dt)/(2 + g dt) and cb = 2 dt eps0 wp^2/(2 + g dt), read with
+ *     E at step n, and subtracted in the E update of Eq. 8 (J before E, as the
+ *     paper orders them), only where wp > 0,
+ *   - a relativistic Boris push of the electron bunch (Sec. III) with
+ *     trilinear gather of the staggered fields,
+ *   - charge-conserving (Esirkepov, first-order shape) deposition of the
+ *     bunch current, also subtracted in the E update.
+ * Absorbing walls are convolutional PML (stretched-coordinate, in place of
+ * the split-field Berenger PML named in Sec. III).
+ *
+ * Conventions for every entry point:
+ *   - All functions return pic_status; nothing throws across the ABI.
+ *   - SI units at the boundary, FP64 host inputs.  Internally the device
+ *     state is FP32 in normalised units; probe accumulators and diagnostics
+ *     are FP64.
+ *   - Host pointers passed in are borrowed for the duration of the call
+ *     only; pic_init copies everything it needs.  The context owns every
+ *     device allocation it makes and pic_destroy frees them.
+ *   - All device work is enqueued on the single HIP stream given in
+ *     pic_opts.stream (NULL = the default stream).  pic_step is
+ *     asynchronous except for the non-finite-field poll every check_every
+ *     steps; pic_probe, pic_read_*, pic_diag, pic_stats and pic_timing
+ *     synchronise that stream.
+ *   - After PIC_EDEVICE or PIC_EUNSTABLE the context is poisoned: every
+ *     later call except pic_destroy and pic_last_error returns PIC_ESTATE.
+ *   - A context is not thread-safe; distinct contexts may be used from
+ *     distinct threads.
+ *
+ * Field storage convention used by pic_read_fields / init fields
+ * ("compact Yee layout"): each of the three components is an nx*ny*nz
+ * array, x fastest (index i + nx*(j + ny*k)), and entry (i,j,k) holds the
+ * component at its staggered Yee position relative to node (i,j,k):
+ *   Ex(i+1/2, j, k)   Ey(i, j+1/2, k)   Ez(i, j, k+1/2)
+ *   Hx(i, j+1/2, k+1/2)   Hy(i+1/2, j, k+1/2)   Hz(i+1/2, j+1/2, k)
+ * Positions on the upper walls (node index n) are not stored: they are
+ * tangential E / normal H on a PEC wall (identically zero) or, on a
+ * periodic axis, copies of node 0.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,    /* bad argument: sizes, boundary codes, CFL bound, particles outside */
+    PIC_ENOMEM = -2,    /* a device or host allocation failed */
+    PIC_EDEVICE = -3,   /* a HIP runtime call failed (context poisoned) */
+    PIC_EUNSTABLE = -4, /* a non-finite field value was detected (context poisoned) */
+    PIC_ESTATE = -5,    /* call on a poisoned context, or wrong call order */
+    PIC_ENOTSUP = -6    /* feature not available for this context */
+} pic_status;
+
+typedef enum { PIC_BC_PEC = 0, PIC_BC_PERIODIC = 1, PIC_BC_CPML = 2 } pic_bc;
+
+typedef enum { PIC_FIELD_E = 0, PIC_FIELD_H = 1, PIC_FIELD_JPOL = 2, PIC_FIELD_JB = 3 } pic_field;
+
+/* Grid and boundaries.  A CPML axis has npml absorbing cells at both ends,
+ * backed by a PEC wall.  Grading: sigma = sigma_max (rho/L)^m with
+ * sigma_max = pml_sigma_scale * 0.8 (m+1)/(eta0 dx), kappa = 1 +
+ * (kappa_max-1)(rho/L)^m, alpha = alpha_max (1 - rho/L) (Roden & Gedney). */
+typedef struct {
+    int32_t nx, ny, nz;  /* cells per axis, each >= 2 */
+    int32_t bc[3];       /* pic_bc per axis */
+    int32_t npml;        /* CPML thickness in cells (used on CPML axes), 2*npml < n */
+    double pml_m;        /* grading order m (e.g. 3) */
+    double pml_sigma_scale;
+    double pml_kappa_max;
+    double pml_alpha_max;
+} pic_grid;
+
+/* One electron species as macro-particles.  Positions in metres inside the
+ * box [0, n dx) per axis; u = gamma v in m/s (at t = -dt/2).  q, m are the
+ * charge and mass of one physical particle, weight the number of physical
+ * particles per macro-particle. */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;
+    const double *ux, *uy, *uz;
+    double q, m, weight;
+} pic_particles;
+
+typedef struct {
+    void *stream;             /* hipStream_t; NULL = default stream */
+    int32_t nprobe;           /* Ez probes (nearest Ez node, ties toward +z) */
+    const double *probe_xyz;  /* [3*nprobe] metres */
+    int32_t nfreq;            /* DFT frequencies */
+    const double *omega;      /* [nfreq] rad/s */
+    int64_t series_len;       /* capacity (steps) of the Ez probe time series; 0 = off */
+    int32_t sort_every;       /* cell sort of the particles every this many steps; 0 = at init only */
+    int32_t check_every;      /* poll the non-finite flag every this many steps; 0 = never */
+    const double *init_E[3];  /* optional E at t=0, compact Yee layout, V/m (NULL = zero);
+                                 tangential entries on PEC/CPML walls are taken as 0 */
+    const double *init_H[3];  /* optional H at t=-dt/2, compact Yee layout, A/m (NULL = zero);
+                                 normal entries on PEC/CPML walls are taken as 0 */
+    int32_t diag;             /* 1: keep the FP64 charge grid needed by the Gauss check */
+    int32_t timing;           /* 1: time every kernel launch with HIP events */
+    int32_t deposit_mode;     /* 0: wavefront-reduced deposit (default), 1: per-lane atomics */
+} pic_opts;
+
+typedef struct pic_ctx pic_ctx;
+
+typedef struct {
+    double field_energy;  /* (eps0 |E|^2 + mu0 |H|^2)/2 dx^3 summed over stored entries, J */
+    double count;         /* live macro-particles */
+    double mean[3];       /* mean position, m */
+    double rms[3];        /* rms size about the mean, m */
+    double umean[3];      /* mean gamma v, m/s */
+    double gauss_max;     /* max |eps0 div E - rho + rho0| over checked nodes, C/m^3 (diag=1) */
+    double rho0_max;      /* max |rho0| at init, C/m^3 (diag=1) */
+    int64_t checked_nodes;/* nodes in the Gauss check: interior, outside CPML and metal */
+} pic_diag_out;
+
+typedef struct {
+    int64_t steps;        /* steps taken */
+    int64_t pushes;       /* particle pushes actually deposited (live particles x steps) */
+    int64_t live;         /* live particles now */
+} pic_stats_out;
+
+/* Library ABI version (PIC_ABI_VERSION). */
+int pic_abi_version(void);
+
+/*
+ * Create a simulation.
+ *   grid       : sizes and boundaries (see pic_grid)
+ *   dx, dt     : cubic cell size (m) and time step (s); dt must satisfy the
+ *                Yee + Drude bound 3 (c dt/dx)^2 + (wp_max dt / 2)^2 <= 1
+ *   wp_map     : [nx*ny*nz] plasma frequency wp per cell, rad/s (Eq. 1), x fastest
+ *   gamma_map  : [nx*ny*nz] collision frequency per cell, 1/s (Eq. 1)
+ *                Cell (i,j,k) owns the edges Ex(i+1/2,j,k), Ey(i,j+1/2,k),
+ *                Ez(i,j,k+1/2); wp = 0 means vacuum (J = 0 there).
+ *   particles  : NULL or n = 0 for a fields-only run
+ *   opts       : NULL for defaults
+ * On success *ctx is a new context.  Errors: PIC_EINVAL (sizes, bc codes,
+ * npml, negative maps, CFL bound, particles outside the box), PIC_ENOMEM,
+ * PIC_EDEVICE.  On error *ctx is NULL.
+ */
+pic_status pic_init(pic_ctx **ctx, const pic_grid *grid, double dx, double dt,
+                    const double *wp_map, const double *gamma_map,
+                    const pic_particles *particles, const pic_opts *opts);
+
+/* Advance nsteps >= 0 full time steps (H, push+deposit, Drude J + E, probes). */
+pic_status pic_step(pic_ctx *ctx, int64_t nsteps);
+
+/*
+ * FP64 probe spectra F[p][m] = sum_n dt Ez_p^n exp(-i omega_m n dt),
+ * n = 1..steps (Sec. IV, Figs. 6-7).  re, im: [nprobe*nfreq] (may be NULL);
+ * series: [nprobe*min(steps, series_len)] Ez samples, step-major (may be NULL).
+ */
+pic_status pic_probe(pic_ctx *ctx, double *re, double *im, double *series);
+
+/*
+ * Gradient of the probe spectral power L = sum_p |F_p(omega0)|^2 with
+ * respect to the per-cell wp and gamma maps, by a reverse-time adjoint of
+ * the field + Drude step with the bunch current held fixed.
+ * Returns PIC_ENOTSUP in this version of the library.
+ */
+pic_status pic_grad(pic_ctx *ctx, double omega0, int64_t nsteps, double *L,
+                    double *dL_dwp, double *dL_dgamma);
+
+/* Copy one field (3 components, compact Yee layout, SI units) to host. */
+pic_status pic_read_fields(pic_ctx *ctx, int which, double *host_out);
+
+/* Copy particles to host, ordered by their original index: out[6*n] =
+ * x[n], y[n], z[n] (m; NaN once a particle has left the box), ux, uy, uz (m/s). */
+pic_status pic_read_particles(pic_ctx *ctx, double *host_out);
+
+/* FP64 diagnostics of the current state. */
+pic_status pic_diag(pic_ctx *ctx, pic_diag_out *out);
+
+/* Step and push counters. */
+pic_status pic_stats(pic_ctx *ctx, pic_stats_out *out);
+
+/*
+ * Per-kernel device time (opts.timing = 1), measured with HIP events on the
+ * context's stream.  names: kernel families in order
+ *   0 h_update, 1 push_deposit, 2 e_update, 3 probe, 4 sort.
+ * ms_total[5], launches[5] receive the accumulated milliseconds and launch
+ * counts since init or the last reset; reset = 1 clears them afterwards.
+ */
+pic_status pic_timing(pic_ctx *ctx, double *ms_total, int64_t *launches, int reset);
+
+/* Destroy a context and free everything it owns.  NULL is a no-op. */
+void pic_destroy(pic_ctx *ctx);
+
+/* Message of the last error on ctx (or of the last failed pic_init when ctx
+ * is NULL).  Owned by the library; valid until the next call on ctx. */
+const char *pic_last_error(const pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -1,0 +1,861 @@
+// Host side of the gfx950 FDTD-PIC library: the C ABI declared in pic.h.
+//
+// pic_init validates the problem, precomputes every coefficient in FP64
+// (Drude ca/cb of Eq. 6 in increment form, CPML b/c/kappa, particle
+// constants), rounds them once to FP32, uploads state, and sorts the
+// particles by cell.  pic_step enqueues, per step, on one stream:
+//   [sort every sort_every steps] -> H update -> push + deposit ->
+//   Drude J + E update -> probe DFT
+// and polls a device non-finite flag every check_every steps.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_internal.hpp"
+
+namespace {
+
+constexpr double kC = 299792458.0;
+constexpr double kMu0 = 1.25663706212e-6;
+constexpr double kEps0 = 1.0 / (kMu0 * kC * kC);
+constexpr double kEta0 = kMu0 * kC;
+constexpr int kFamilies = 5;  // h_update, push_deposit, e_update, probe, sort
+
+thread_local std::string g_init_error;
+
+}  // namespace
+
+struct pic_ctx {
+    int n[3] = {0, 0, 0};
+    int bc[3] = {0, 0, 0};
+    int per[3] = {0, 0, 0};
+    int npml = 0;
+    double dx = 0, dt = 0, S = 0;
+    hipStream_t stream = nullptr;
+    bool poisoned = false;
+    std::string err;
+    std::vector<void *> allocs;
+
+    float *E[3] = {nullptr, nullptr, nullptr};
+    float *H[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int hcur = 0;
+    pic::PmlAxis pml[3];
+
+    int mlo[3] = {0, 0, 0}, mhi[3] = {0, 0, 0};
+    bool has_metal = false;
+    float *Jp[3] = {nullptr, nullptr, nullptr};
+    float2 *coef = nullptr;
+
+    float *Jb[3] = {nullptr, nullptr, nullptr};
+
+    int np = 0;
+    float *P[2][6] = {};
+    int *pid[2] = {nullptr, nullptr};
+    int pcur = 0;
+    int *key = nullptr, *rank = nullptr, *counts = nullptr, *box = nullptr, *scan_tmp = nullptr;
+    int scan_len = 0;
+    float ah = 0.f, qd = 0.f;
+    double q = 0, m = 0, w = 0;
+    unsigned long long *d_pushes = nullptr;
+    int *d_nan = nullptr;
+    int deposit_mode = 0;
+
+    int nprobe = 0, nfreq = 0;
+    int *pidx = nullptr;
+    double *omega = nullptr, *fre = nullptr, *fim = nullptr;
+    float *series = nullptr;
+    long long series_len = 0;
+
+    bool diag = false;
+    double *rho = nullptr, *rho0 = nullptr, *acc = nullptr;
+    int *d_live = nullptr;
+
+    long long step = 0;
+    int sort_every = 0, check_every = 0;
+    long long since_sort = 0;
+
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kFamilies];
+};
+
+namespace {
+
+pic_status fail(pic_ctx *c, pic_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) {
+        c->err = buf;
+        if (st == PIC_EDEVICE || st == PIC_EUNSTABLE) c->poisoned = true;
+    } else {
+        g_init_error = buf;
+    }
+    return st;
+}
+
+#define HIP_TRY(ctx, call)                                                                         \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((ctx), PIC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
+    } while (0)
+
+template <typename T>
+pic_status dalloc(pic_ctx *c, T **p, size_t count)
+{
+    void *q = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, e == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EDEVICE,
+                    "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->allocs.push_back(q);
+    *p = (T *)q;
+    return PIC_OK;
+}
+
+#define TRY(x)                                                                                     \
+    do {                                                                                           \
+        pic_status s_ = (x);                                                                       \
+        if (s_ != PIC_OK) return s_;                                                               \
+    } while (0)
+
+// CPML coefficients at position `pos` (cells) along an axis of n cells.
+void cpml_coeff(const pic_grid &g, int npml, int n, double pos, double dx, double dt, float &b,
+                float &c, float &ik)
+{
+    const double L = (double)npml;
+    double rho = 0.0;
+    if (pos < L) rho = L - pos;
+    if (pos > (double)n - L) rho = pos - ((double)n - L);
+    if (rho <= 0.0) {
+        b = 1.f;
+        c = 0.f;
+        ik = 1.f;
+        return;
+    }
+    const double m = g.pml_m;
+    const double r = rho / L;
+    const double smax = g.pml_sigma_scale * 0.8 * (m + 1.0) / (kEta0 * dx);
+    const double sig = smax * std::pow(r, m);
+    const double kap = 1.0 + (g.pml_kappa_max - 1.0) * std::pow(r, m);
+    const double alp = g.pml_alpha_max * (1.0 - r);
+    const double bb = std::exp(-(sig / kap + alp) * dt / kEps0);
+    const double cc = sig > 0.0 ? sig * (bb - 1.0) / (sig * kap + kap * kap * alp) : 0.0;
+    b = (float)bb;
+    c = (float)cc;
+    ik = (float)(1.0 / kap);
+}
+
+pic::FieldArgs field_args(pic_ctx *c, bool for_h)
+{
+    pic::FieldArgs a{};
+    a.nx = c->n[0];
+    a.ny = c->n[1];
+    a.nz = c->n[2];
+    for (int d = 0; d < 3; ++d) {
+        a.per[d] = c->per[d];
+        a.pml[d] = c->pml[d];
+        a.mlo[d] = c->mlo[d];
+        a.mhi[d] = c->mhi[d];
+    }
+    a.S = (float)c->S;
+    for (int d = 0; d < 3; ++d) {
+        a.E[d] = c->E[d];
+        if (for_h) {
+            a.Hin[d] = c->H[c->hcur][d];
+            a.Hout[d] = c->H[1 - c->hcur][d];
+        } else {
+            a.Hin[d] = c->H[c->hcur][d];
+            a.Hout[d] = nullptr;
+        }
+        a.Jp[d] = c->Jp[d];
+        a.Jb[d] = c->Jb[d];
+    }
+    a.coef = c->coef;
+    if (!c->has_metal) {
+        for (int d = 0; d < 3; ++d) a.mlo[d] = a.mhi[d] = 0;
+    }
+    a.pbox = c->np > 0 ? c->box : nullptr;
+    a.margin = 3 + (int)std::ceil((double)(c->since_sort + 1) * c->S);
+    a.nan_flag = c->d_nan;
+    return a;
+}
+
+void tstart(pic_ctx *c, int fam)
+{
+    if (!c->timing) return;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, c->stream);
+    c->ev[fam].push_back({a, b});
+}
+
+void tstop(pic_ctx *c, int fam)
+{
+    if (!c->timing) return;
+    (void)hipEventRecord(c->ev[fam].back().second, c->stream);
+}
+
+pic_status do_sort(pic_ctx *c)
+{
+    if (c->np <= 0) return PIC_OK;
+    pic::SortArgs s{};
+    s.n = c->np;
+    s.nx = c->n[0];
+    s.ny = c->n[1];
+    s.nz = c->n[2];
+    s.ncell = c->n[0] * c->n[1] * c->n[2];
+    for (int q = 0; q < 6; ++q) {
+        s.src[q] = c->P[c->pcur][q];
+        s.dst[q] = c->P[1 - c->pcur][q];
+    }
+    s.id_src = c->pid[c->pcur];
+    s.id_dst = c->pid[1 - c->pcur];
+    s.key = c->key;
+    s.rank = c->rank;
+    s.counts = c->counts;
+    s.box = c->box;
+    tstart(c, 4);
+    pic::launch_sort(s, c->scan_tmp, c->scan_len, c->stream);
+    tstop(c, 4);
+    HIP_TRY(c, hipGetLastError());
+    c->pcur = 1 - c->pcur;
+    c->since_sort = 0;
+    return PIC_OK;
+}
+
+pic::DiagArgs diag_args(pic_ctx *c)
+{
+    pic::DiagArgs a{};
+    a.nx = c->n[0];
+    a.ny = c->n[1];
+    a.nz = c->n[2];
+    for (int d = 0; d < 3; ++d) {
+        a.per[d] = c->per[d];
+        a.npml[d] = c->bc[d] == PIC_BC_CPML ? c->npml : 0;
+        a.mlo[d] = c->has_metal ? c->mlo[d] : 0;
+        a.mhi[d] = c->has_metal ? c->mhi[d] : -2;
+    }
+    for (int d = 0; d < 3; ++d) {
+        a.E[d] = c->E[d];
+        a.H[d] = c->H[c->hcur][d];
+    }
+    a.np = c->np;
+    if (c->np > 0) {
+        a.x = c->P[c->pcur][0];
+        a.y = c->P[c->pcur][1];
+        a.z = c->P[c->pcur][2];
+        a.ux = c->P[c->pcur][3];
+        a.uy = c->P[c->pcur][4];
+        a.uz = c->P[c->pcur][5];
+    }
+    a.qw_over_vol = c->q * c->w / (c->dx * c->dx * c->dx);
+    a.eps0_over_dx = kEps0 / c->dx;
+    a.acc = c->acc;
+    return a;
+}
+
+bool finite_nonneg(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!(std::isfinite(p[i]) && p[i] >= 0.0)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_abi_version(void) { return PIC_ABI_VERSION; }
+
+const char *pic_last_error(const pic_ctx *ctx)
+{
+    if (!ctx) return g_init_error.c_str();
+    return ctx->err.c_str();
+}
+
+void pic_destroy(pic_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    for (int f = 0; f < kFamilies; ++f)
+        for (auto &e : ctx->ev[f]) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    delete ctx;
+}
+
+static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double dt,
+                            const double *wp_map, const double *gamma_map,
+                            const pic_particles *parts, const pic_opts *opts)
+{
+    const pic_grid &g = *grid;
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d) {
+        if (g.bc[d] < PIC_BC_PEC || g.bc[d] > PIC_BC_CPML)
+            return fail(c, PIC_EINVAL, "bc[%d] = %d is not a pic_bc code", d, g.bc[d]);
+        const int nmin = g.bc[d] == PIC_BC_PERIODIC ? 1 : 2;
+        if (nn[d] < nmin) return fail(c, PIC_EINVAL, "axis %d has %d cells (minimum %d)", d, nn[d], nmin);
+        c->n[d] = nn[d];
+        c->bc[d] = g.bc[d];
+        c->per[d] = g.bc[d] == PIC_BC_PERIODIC;
+    }
+    const long long ncell = (long long)nn[0] * nn[1] * nn[2];
+    if (ncell > 0x7fffffffLL) return fail(c, PIC_EINVAL, "grid of %lld cells exceeds 2^31-1", ncell);
+    bool any_cpml = false;
+    for (int d = 0; d < 3; ++d) any_cpml = any_cpml || g.bc[d] == PIC_BC_CPML;
+    if (any_cpml) {
+        if (g.npml < 1) return fail(c, PIC_EINVAL, "npml = %d must be >= 1 on a CPML axis", g.npml);
+        for (int d = 0; d < 3; ++d)
+            if (g.bc[d] == PIC_BC_CPML && 2 * g.npml >= nn[d])
+                return fail(c, PIC_EINVAL, "2*npml = %d must be < n = %d on axis %d", 2 * g.npml, nn[d], d);
+        if (!(g.pml_m >= 0.0) || !(g.pml_sigma_scale >= 0.0) || !(g.pml_kappa_max >= 1.0) ||
+            !(g.pml_alpha_max >= 0.0))
+            return fail(c, PIC_EINVAL, "CPML parameters out of range (m, sigma scale >= 0, kappa_max >= 1, alpha_max >= 0)");
+    }
+    c->npml = any_cpml ? g.npml : 0;
+    if (!(dx > 0.0) || !(dt > 0.0) || !std::isfinite(dx) || !std::isfinite(dt))
+        return fail(c, PIC_EINVAL, "dx and dt must be positive and finite");
+    if (!wp_map || !gamma_map) return fail(c, PIC_EINVAL, "wp_map and gamma_map are required");
+    if (!finite_nonneg(wp_map, (size_t)ncell) || !finite_nonneg(gamma_map, (size_t)ncell))
+        return fail(c, PIC_EINVAL, "wp_map / gamma_map must be finite and >= 0");
+    c->dx = dx;
+    c->dt = dt;
+    c->S = kC * dt / dx;
+    double wpmax = 0.0;
+    for (long long q = 0; q < ncell; ++q) wpmax = std::max(wpmax, wp_map[q]);
+    const double cfl = 3.0 * c->S * c->S + 0.25 * (wpmax * dt) * (wpmax * dt);
+    if (cfl > 1.0 + 1e-12)
+        return fail(c, PIC_EINVAL, "time step violates 3 (c dt/dx)^2 + (wp dt/2)^2 <= 1 (value %.6g)", cfl);
+
+    pic_opts o{};
+    if (opts) o = *opts;
+    c->stream = (hipStream_t)o.stream;
+    c->sort_every = o.sort_every > 0 ? o.sort_every : 0;
+    c->check_every = o.check_every > 0 ? o.check_every : 0;
+    c->timing = o.timing != 0;
+    c->diag = o.diag != 0;
+    c->deposit_mode = o.deposit_mode == 1 ? 1 : 0;
+    if (o.nprobe < 0 || o.nfreq < 0 || o.series_len < 0)
+        return fail(c, PIC_EINVAL, "nprobe, nfreq and series_len must be >= 0");
+    if (o.nprobe > 256) return fail(c, PIC_EINVAL, "at most 256 probes");
+    if (o.nprobe > 0 && !o.probe_xyz) return fail(c, PIC_EINVAL, "probe_xyz is NULL");
+    if (o.nfreq > 0 && !o.omega) return fail(c, PIC_EINVAL, "omega is NULL");
+
+    // particles: validate on the host
+    const bool with_p = parts && parts->n > 0;
+    if (with_p) {
+        const pic_particles &P = *parts;
+        if (P.n > 0x7fffffffLL) return fail(c, PIC_EINVAL, "at most 2^31-1 particles");
+        if (!P.x || !P.y || !P.z || !P.ux || !P.uy || !P.uz)
+            return fail(c, PIC_EINVAL, "particle arrays must be non-NULL");
+        if (!(P.m > 0.0) || !std::isfinite(P.q) || !std::isfinite(P.weight))
+            return fail(c, PIC_EINVAL, "particle mass must be > 0, charge and weight finite");
+        const double *X[3] = {P.x, P.y, P.z};
+        for (long long i = 0; i < P.n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                const double v = X[d][i] / dx;
+                if (!(v >= 0.0 && v < (double)nn[d]))
+                    return fail(c, PIC_EINVAL, "particle %lld lies outside the box on axis %d", i, d);
+            }
+    }
+
+    // ---- device allocations ----
+    const size_t N = (size_t)ncell;
+    for (int d = 0; d < 3; ++d) {
+        TRY(dalloc(c, &c->E[d], N));
+        TRY(dalloc(c, &c->H[0][d], N));
+        TRY(dalloc(c, &c->H[1][d], N));
+        HIP_TRY(c, hipMemsetAsync(c->E[d], 0, N * 4, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->H[0][d], 0, N * 4, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->H[1][d], 0, N * 4, c->stream));
+    }
+    TRY(dalloc(c, &c->d_nan, 1));
+    TRY(dalloc(c, &c->d_pushes, 1));
+    HIP_TRY(c, hipMemsetAsync(c->d_nan, 0, 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_pushes, 0, 8, c->stream));
+    TRY(dalloc(c, &c->acc, 16));
+    TRY(dalloc(c, &c->d_live, 1));
+
+    // host staging kept alive until the final synchronisation
+    std::vector<std::vector<float>> stage;
+    auto upload = [&](void *dst, const void *src, size_t bytes) -> pic_status {
+        HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+        return PIC_OK;
+    };
+
+    // optional initial fields (compact Yee layout, SI).  On a PEC wall (also
+    // behind a CPML) tangential E and normal H vanish: the stored lower-wall
+    // planes are zeroed, as the upper-wall planes are implicitly.
+    auto on_wall = [&](size_t q, int comp, bool electric) {
+        const int id[3] = {(int)(q % nn[0]), (int)((q / nn[0]) % nn[1]), (int)(q / ((size_t)nn[0] * nn[1]))};
+        for (int a = 0; a < 3; ++a) {
+            if (c->per[a] || id[a] != 0) continue;
+            if (electric ? a != comp : a == comp) return true;
+        }
+        return false;
+    };
+    for (int d = 0; d < 3; ++d) {
+        if (o.init_E[d]) {
+            stage.emplace_back(N);
+            for (size_t q = 0; q < N; ++q) stage.back()[q] = on_wall(q, d, true) ? 0.f : (float)o.init_E[d][q];
+            TRY(upload(c->E[d], stage.back().data(), N * 4));
+        }
+        if (o.init_H[d]) {
+            stage.emplace_back(N);
+            for (size_t q = 0; q < N; ++q)
+                stage.back()[q] = on_wall(q, d, false) ? 0.f : (float)(o.init_H[d][q] * kEta0);
+            TRY(upload(c->H[0][d], stage.back().data(), N * 4));
+        }
+    }
+
+    // Drude coefficients on the metal bounding box (cell owns its three edges)
+    int lo[3] = {nn[0], nn[1], nn[2]}, hi[3] = {-1, -1, -1};
+    for (int k = 0; k < nn[2]; ++k)
+        for (int j = 0; j < nn[1]; ++j)
+            for (int i = 0; i < nn[0]; ++i) {
+                const size_t q = (size_t)i + (size_t)nn[0] * ((size_t)j + (size_t)nn[1] * k);
+                if (wp_map[q] > 0.0) {
+                    const int id[3] = {i, j, k};
+                    for (int d = 0; d < 3; ++d) {
+                        lo[d] = std::min(lo[d], id[d]);
+                        hi[d] = std::max(hi[d], id[d]);
+                    }
+                }
+            }
+    c->has_metal = hi[0] >= 0;
+    if (c->has_metal) {
+        for (int d = 0; d < 3; ++d) {
+            c->mlo[d] = lo[d];
+            c->mhi[d] = hi[d] + 1;
+        }
+        const int wx = c->mhi[0] - c->mlo[0], wy = c->mhi[1] - c->mlo[1], wz = c->mhi[2] - c->mlo[2];
+        const size_t nb = (size_t)wx * wy * wz;
+        std::vector<float> cf(2 * nb);
+        for (int k = 0; k < wz; ++k)
+            for (int j = 0; j < wy; ++j)
+                for (int i = 0; i < wx; ++i) {
+                    const size_t q = (size_t)(i + c->mlo[0]) +
+                                     (size_t)nn[0] * ((size_t)(j + c->mlo[1]) + (size_t)nn[1] * (k + c->mlo[2]));
+                    const double wp = wp_map[q], gm = gamma_map[q];
+                    // Eq. 6 rescaled by dt/eps0: Jt += cbt E - d Jt
+                    const double cbt = 2.0 * (wp * dt) * (wp * dt) / (2.0 + gm * dt);
+                    const double dd = 2.0 * gm * dt / (2.0 + gm * dt);
+                    const size_t b = (size_t)i + (size_t)wx * ((size_t)j + (size_t)wy * k);
+                    cf[2 * b] = wp > 0.0 ? (float)cbt : 0.f;
+                    cf[2 * b + 1] = wp > 0.0 ? (float)dd : 0.f;
+                }
+        TRY(dalloc(c, &c->coef, nb));
+        stage.emplace_back(std::move(cf));
+        TRY(upload(c->coef, stage.back().data(), 2 * nb * 4));
+        for (int d = 0; d < 3; ++d) {
+            TRY(dalloc(c, &c->Jp[d], nb));
+            HIP_TRY(c, hipMemsetAsync(c->Jp[d], 0, nb * 4, c->stream));
+        }
+    }
+
+    // CPML tables and psi slabs
+    for (int d = 0; d < 3; ++d) {
+        pic::PmlAxis &P = c->pml[d];
+        P = pic::PmlAxis{};
+        if (g.bc[d] != PIC_BC_CPML) continue;
+        P.on = 1;
+        P.npml = g.npml;
+        const int n = nn[d];
+        std::vector<float> tab(6 * (size_t)n);
+        for (int i = 0; i < n; ++i) {
+            cpml_coeff(g, g.npml, n, (double)i, dx, dt, tab[0 * n + i], tab[1 * n + i], tab[2 * n + i]);
+            cpml_coeff(g, g.npml, n, i + 0.5, dx, dt, tab[3 * n + i], tab[4 * n + i], tab[5 * n + i]);
+        }
+        float *dtab = nullptr;
+        TRY(dalloc(c, &dtab, tab.size()));
+        stage.emplace_back(std::move(tab));
+        TRY(upload(dtab, stage.back().data(), stage.back().size() * 4));
+        P.bE = dtab;
+        P.cE = dtab + n;
+        P.kE = dtab + 2 * n;
+        P.bH = dtab + 3 * n;
+        P.cH = dtab + 4 * n;
+        P.kH = dtab + 5 * n;
+        const size_t slab = (size_t)2 * g.npml * (N / (size_t)n);
+        for (int q = 0; q < 2; ++q) {
+            TRY(dalloc(c, &P.psiE[q], slab));
+            TRY(dalloc(c, &P.psiH[q], slab));
+            HIP_TRY(c, hipMemsetAsync(P.psiE[q], 0, slab * 4, c->stream));
+            HIP_TRY(c, hipMemsetAsync(P.psiH[q], 0, slab * 4, c->stream));
+        }
+    }
+
+    // probes: nearest Ez node, i, j rounded half up, k = floor(z/dx)
+    c->nprobe = o.nprobe;
+    c->nfreq = o.nfreq;
+    c->series_len = o.series_len;
+    if (c->nprobe > 0) {
+        std::vector<int> pidx(c->nprobe);
+        for (int p = 0; p < c->nprobe; ++p) {
+            const int i = (int)std::floor(o.probe_xyz[3 * p] / dx + 0.5);
+            const int j = (int)std::floor(o.probe_xyz[3 * p + 1] / dx + 0.5);
+            const int k = (int)std::floor(o.probe_xyz[3 * p + 2] / dx);
+            if (i < 0 || i >= nn[0] || j < 0 || j >= nn[1] || k < 0 || k >= nn[2])
+                return fail(c, PIC_EINVAL, "probe %d maps to Ez node (%d,%d,%d) outside the stored grid", p, i, j, k);
+            pidx[p] = i + nn[0] * (j + nn[1] * k);
+        }
+        TRY(dalloc(c, &c->pidx, c->nprobe));
+        HIP_TRY(c, hipMemcpyAsync(c->pidx, pidx.data(), 4 * pidx.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const size_t nf = (size_t)c->nprobe * c->nfreq;
+        TRY(dalloc(c, &c->omega, c->nfreq > 0 ? c->nfreq : 1));
+        TRY(dalloc(c, &c->fre, nf ? nf : 1));
+        TRY(dalloc(c, &c->fim, nf ? nf : 1));
+        if (c->nfreq > 0)
+            HIP_TRY(c, hipMemcpyAsync(c->omega, o.omega, 8 * (size_t)c->nfreq, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->fre, 0, 8 * (nf ? nf : 1), c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->fim, 0, 8 * (nf ? nf : 1), c->stream));
+        if (c->series_len > 0) TRY(dalloc(c, &c->series, (size_t)c->series_len * c->nprobe));
+    }
+
+    // particles: FP32 cell-unit positions, u/c
+    if (with_p) {
+        const pic_particles &P = *parts;
+        c->np = (int)P.n;
+        c->q = P.q;
+        c->m = P.m;
+        c->w = P.weight;
+        c->ah = (float)(P.q * dt / (2.0 * P.m * kC));
+        c->qd = (float)(-P.q * P.weight / (kEps0 * dx * dx));
+        const double *src[6] = {P.x, P.y, P.z, P.ux, P.uy, P.uz};
+        for (int s = 0; s < 2; ++s) {
+            for (int q = 0; q < 6; ++q) TRY(dalloc(c, &c->P[s][q], (size_t)c->np));
+            TRY(dalloc(c, &c->pid[s], (size_t)c->np));
+        }
+        for (int q = 0; q < 6; ++q) {
+            stage.emplace_back((size_t)c->np);
+            const double sc = q < 3 ? 1.0 / dx : 1.0 / kC;
+            for (int i = 0; i < c->np; ++i) stage.back()[i] = (float)(src[q][i] * sc);
+            if (q < 3) {
+                // keep the FP32 cell coordinate inside [0, n) after rounding
+                for (int i = 0; i < c->np; ++i)
+                    if (stage.back()[i] >= (float)nn[q]) stage.back()[i] = std::nextafter((float)nn[q], 0.f);
+            }
+            TRY(upload(c->P[0][q], stage.back().data(), (size_t)c->np * 4));
+        }
+        std::vector<int> ids(c->np);
+        for (int i = 0; i < c->np; ++i) ids[i] = i;
+        HIP_TRY(c, hipMemcpyAsync(c->pid[0], ids.data(), 4 * (size_t)c->np, hipMemcpyHostToDevice, c->stream));
+        TRY(dalloc(c, &c->key, (size_t)c->np));
+        TRY(dalloc(c, &c->rank, (size_t)c->np));
+        TRY(dalloc(c, &c->counts, (size_t)ncell + 1));
+        TRY(dalloc(c, &c->box, 6));
+        c->scan_len = pic::scan_tmp_size((int)ncell + 1);
+        TRY(dalloc(c, &c->scan_tmp, (size_t)c->scan_len));
+        for (int d = 0; d < 3; ++d) {
+            TRY(dalloc(c, &c->Jb[d], N));
+            HIP_TRY(c, hipMemsetAsync(c->Jb[d], 0, N * 4, c->stream));
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        TRY(do_sort(c));
+        if (c->diag) {
+            const size_t nodes = (size_t)(nn[0] + 1) * (nn[1] + 1) * (nn[2] + 1);
+            TRY(dalloc(c, &c->rho, nodes));
+            TRY(dalloc(c, &c->rho0, nodes));
+            HIP_TRY(c, hipMemsetAsync(c->rho0, 0, nodes * 8, c->stream));
+            pic::DiagArgs a = diag_args(c);
+            a.rho = c->rho0;
+            pic::launch_rho(a, c->stream);
+            HIP_TRY(c, hipGetLastError());
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipGetLastError());
+    c->since_sort = 0;
+    return PIC_OK;
+}
+
+pic_status pic_init(pic_ctx **ctx, const pic_grid *grid, double dx, double dt, const double *wp_map,
+                    const double *gamma_map, const pic_particles *particles, const pic_opts *opts)
+{
+    if (!ctx) return fail(nullptr, PIC_EINVAL, "ctx is NULL");
+    *ctx = nullptr;
+    if (!grid) return fail(nullptr, PIC_EINVAL, "grid is NULL");
+    pic_ctx *c = new (std::nothrow) pic_ctx();
+    if (!c) return fail(nullptr, PIC_ENOMEM, "out of host memory");
+    pic_status st = init_impl(c, grid, dx, dt, wp_map, gamma_map, particles, opts);
+    if (st != PIC_OK) {
+        g_init_error = c->err;
+        pic_destroy(c);
+        return st;
+    }
+    *ctx = c;
+    return PIC_OK;
+}
+
+#define CHECK_CTX(c)                                                                               \
+    do {                                                                                           \
+        if (!(c)) return fail(nullptr, PIC_EINVAL, "ctx is NULL");                                 \
+        if ((c)->poisoned) return PIC_ESTATE;                                                      \
+    } while (0)
+
+pic_status pic_step(pic_ctx *c, int64_t nsteps)
+{
+    CHECK_CTX(c);
+    if (nsteps < 0) return fail(c, PIC_EINVAL, "nsteps must be >= 0");
+    for (int64_t it = 0; it < nsteps; ++it) {
+        if (c->np > 0 && c->sort_every > 0 && c->since_sort >= c->sort_every) TRY(do_sort(c));
+        // 1. H^{n+1/2}
+        pic::FieldArgs fh = field_args(c, true);
+        tstart(c, 0);
+        pic::launch_h_update(fh, c->stream);
+        tstop(c, 0);
+        // 2. gather E^n, B^n; Boris; move; deposit J_b^{n+1/2}
+        if (c->np > 0) {
+            pic::PartArgs pa{};
+            pa.n = c->np;
+            pa.x = c->P[c->pcur][0];
+            pa.y = c->P[c->pcur][1];
+            pa.z = c->P[c->pcur][2];
+            pa.ux = c->P[c->pcur][3];
+            pa.uy = c->P[c->pcur][4];
+            pa.uz = c->P[c->pcur][5];
+            pa.nx = c->n[0];
+            pa.ny = c->n[1];
+            pa.nz = c->n[2];
+            for (int d = 0; d < 3; ++d) {
+                pa.per[d] = c->per[d];
+                pa.E[d] = c->E[d];
+                pa.Hold[d] = c->H[c->hcur][d];
+                pa.Hnew[d] = c->H[1 - c->hcur][d];
+                pa.Jb[d] = c->Jb[d];
+            }
+            pa.S = (float)c->S;
+            pa.ah = c->ah;
+            pa.qd = c->qd;
+            pa.pushes = c->d_pushes;
+            tstart(c, 1);
+            pic::launch_push_deposit(pa, c->deposit_mode, c->stream);
+            tstop(c, 1);
+        }
+        c->hcur = 1 - c->hcur;
+        // 3-4. Drude J^{n+1/2} (Eq. 6), E^{n+1} (Eq. 8 with the bunch current)
+        pic::FieldArgs fe = field_args(c, false);
+        tstart(c, 2);
+        pic::launch_e_update(fe, c->stream);
+        tstop(c, 2);
+        c->step++;
+        c->since_sort++;
+        // 5. probes
+        if (c->nprobe > 0) {
+            pic::ProbeArgs pr{};
+            pr.nprobe = c->nprobe;
+            pr.nfreq = c->nfreq;
+            pr.pidx = c->pidx;
+            pr.omega = c->omega;
+            pr.fre = c->fre;
+            pr.fim = c->fim;
+            pr.series = c->series;
+            pr.series_len = c->series_len;
+            pr.step = c->step;
+            pr.dt = c->dt;
+            pr.Ez = c->E[2];
+            pr.nan_flag = c->d_nan;
+            tstart(c, 3);
+            pic::launch_probe(pr, c->stream);
+            tstop(c, 3);
+        }
+        HIP_TRY(c, hipGetLastError());
+        if (c->check_every > 0 && c->step % c->check_every == 0) {
+            int flag = 0;
+            HIP_TRY(c, hipMemcpyAsync(&flag, c->d_nan, 4, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (flag) return fail(c, PIC_EUNSTABLE, "non-finite field value detected by step %lld", c->step);
+        }
+    }
+    return PIC_OK;
+}
+
+pic_status pic_probe(pic_ctx *c, double *re, double *im, double *series)
+{
+    CHECK_CTX(c);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const size_t nf = (size_t)c->nprobe * c->nfreq;
+    if (nf && re) HIP_TRY(c, hipMemcpy(re, c->fre, nf * 8, hipMemcpyDeviceToHost));
+    if (nf && im) HIP_TRY(c, hipMemcpy(im, c->fim, nf * 8, hipMemcpyDeviceToHost));
+    if (series && c->series) {
+        const long long ns = std::min<long long>(c->step, c->series_len);
+        std::vector<float> tmp((size_t)ns * c->nprobe);
+        if (!tmp.empty())
+            HIP_TRY(c, hipMemcpy(tmp.data(), c->series, tmp.size() * 4, hipMemcpyDeviceToHost));
+        for (size_t q = 0; q < tmp.size(); ++q) series[q] = tmp[q];
+    }
+    return PIC_OK;
+}
+
+pic_status pic_grad(pic_ctx *c, double omega0, int64_t nsteps, double *L, double *dL_dwp,
+                    double *dL_dgamma)
+{
+    CHECK_CTX(c);
+    (void)omega0;
+    (void)nsteps;
+    (void)L;
+    (void)dL_dwp;
+    (void)dL_dgamma;
+    return fail(c, PIC_ENOTSUP, "pic_grad is not available in this version of the library");
+}
+
+pic_status pic_read_fields(pic_ctx *c, int which, double *out)
+{
+    CHECK_CTX(c);
+    if (!out) return fail(c, PIC_EINVAL, "host_out is NULL");
+    const size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<float> tmp(N);
+    for (int d = 0; d < 3; ++d) {
+        double *dst = out + d * N;
+        if (which == PIC_FIELD_E || which == PIC_FIELD_H || which == PIC_FIELD_JB) {
+            const float *src = which == PIC_FIELD_E ? c->E[d] : which == PIC_FIELD_H ? c->H[c->hcur][d] : c->Jb[d];
+            const double sc = which == PIC_FIELD_H ? 1.0 / kEta0 : which == PIC_FIELD_JB ? kEps0 / c->dt : 1.0;
+            if (!src) {
+                for (size_t q = 0; q < N; ++q) dst[q] = 0.0;
+                continue;
+            }
+            HIP_TRY(c, hipMemcpy(tmp.data(), src, N * 4, hipMemcpyDeviceToHost));
+            for (size_t q = 0; q < N; ++q) dst[q] = tmp[q] * sc;
+        } else if (which == PIC_FIELD_JPOL) {
+            for (size_t q = 0; q < N; ++q) dst[q] = 0.0;
+            if (!c->has_metal) continue;
+            const int wx = c->mhi[0] - c->mlo[0], wy = c->mhi[1] - c->mlo[1], wz = c->mhi[2] - c->mlo[2];
+            std::vector<float> box((size_t)wx * wy * wz);
+            HIP_TRY(c, hipMemcpy(box.data(), c->Jp[d], box.size() * 4, hipMemcpyDeviceToHost));
+            const double sc = kEps0 / c->dt;
+            for (int k = 0; k < wz; ++k)
+                for (int j = 0; j < wy; ++j)
+                    for (int i = 0; i < wx; ++i)
+                        dst[(size_t)(i + c->mlo[0]) + (size_t)c->n[0] * ((size_t)(j + c->mlo[1]) + (size_t)c->n[1] * (k + c->mlo[2]))] =
+                            box[(size_t)i + (size_t)wx * ((size_t)j + (size_t)wy * k)] * sc;
+        } else {
+            return fail(c, PIC_EINVAL, "unknown field %d", which);
+        }
+    }
+    return PIC_OK;
+}
+
+pic_status pic_read_particles(pic_ctx *c, double *out)
+{
+    CHECK_CTX(c);
+    if (c->np == 0) return PIC_OK;
+    if (!out) return fail(c, PIC_EINVAL, "host_out is NULL");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const size_t n = (size_t)c->np;
+    std::vector<float> tmp(6 * n);
+    std::vector<int> ids(n);
+    for (int q = 0; q < 6; ++q)
+        HIP_TRY(c, hipMemcpy(tmp.data() + q * n, c->P[c->pcur][q], n * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(ids.data(), c->pid[c->pcur], n * 4, hipMemcpyDeviceToHost));
+    for (size_t p = 0; p < n; ++p) {
+        const int id = ids[p];
+        if (id < 0 || (size_t)id >= n) return fail(c, PIC_EDEVICE, "particle id table corrupted");
+        const bool dead = !(tmp[p] >= 0.f && tmp[n + p] >= 0.f && tmp[2 * n + p] >= 0.f &&
+                            tmp[p] < (float)c->n[0] && tmp[n + p] < (float)c->n[1] &&
+                            tmp[2 * n + p] < (float)c->n[2]);
+        for (int q = 0; q < 6; ++q) {
+            const double sc = q < 3 ? c->dx : kC;
+            out[q * n + id] = (dead && q < 3) ? NAN : tmp[q * n + p] * sc;
+        }
+    }
+    return PIC_OK;
+}
+
+pic_status pic_diag(pic_ctx *c, pic_diag_out *out)
+{
+    CHECK_CTX(c);
+    if (!out) return fail(c, PIC_EINVAL, "out is NULL");
+    HIP_TRY(c, hipMemsetAsync(c->acc, 0, 16 * 8, c->stream));
+    pic::DiagArgs a = diag_args(c);
+    if (c->diag && c->np > 0) {
+        const size_t nodes = (size_t)(c->n[0] + 1) * (c->n[1] + 1) * (c->n[2] + 1);
+        HIP_TRY(c, hipMemsetAsync(c->rho, 0, nodes * 8, c->stream));
+        a.rho = c->rho;
+        pic::launch_rho(a, c->stream);
+        a.rho0 = c->rho0;
+    }
+    pic::launch_diag_reduce(a, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    double acc[16];
+    HIP_TRY(c, hipMemcpyAsync(acc, c->acc, sizeof acc, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::memset(out, 0, sizeof *out);
+    out->field_energy = 0.5 * kEps0 * acc[0] * c->dx * c->dx * c->dx;
+    const double cnt = acc[1];
+    out->count = cnt;
+    for (int d = 0; d < 3; ++d) {
+        const double mean = cnt > 0 ? acc[2 + d] / cnt : 0.0;
+        const double var = cnt > 0 ? acc[5 + d] / cnt - mean * mean : 0.0;
+        out->mean[d] = mean * c->dx;
+        out->rms[d] = (var > 0 ? std::sqrt(var) : 0.0) * c->dx;
+        out->umean[d] = (cnt > 0 ? acc[8 + d] / cnt : 0.0) * kC;
+    }
+    out->gauss_max = acc[11];
+    out->rho0_max = acc[12];
+    out->checked_nodes = (int64_t)acc[13];
+    return PIC_OK;
+}
+
+pic_status pic_stats(pic_ctx *c, pic_stats_out *out)
+{
+    CHECK_CTX(c);
+    if (!out) return fail(c, PIC_EINVAL, "out is NULL");
+    unsigned long long pushes = 0;
+    HIP_TRY(c, hipMemcpyAsync(&pushes, c->d_pushes, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out->steps = c->step;
+    out->pushes = (int64_t)pushes;
+    out->live = 0;
+    if (c->np > 0) {
+        pic_diag_out d;
+        pic_status st = pic_diag(c, &d);
+        if (st != PIC_OK) return st;
+        out->live = (int64_t)d.count;
+    }
+    return PIC_OK;
+}
+
+pic_status pic_timing(pic_ctx *c, double *ms_total, int64_t *launches, int reset)
+{
+    CHECK_CTX(c);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int f = 0; f < kFamilies; ++f) {
+        double tot = 0.0;
+        for (auto &e : c->ev[f]) {
+            float ms = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, e.first, e.second));
+            tot += ms;
+        }
+        if (ms_total) ms_total[f] = tot;
+        if (launches) launches[f] = (int64_t)c->ev[f].size();
+        if (reset) {
+            for (auto &e : c->ev[f]) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
+            c->ev[f].clear();
+        }
+    }
+    return PIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+"""ctypes binding of libpic.so (include/pic.h): argument marshalling only.
+
+Every step of the simulation runs in the library's HIP kernels; this module
+converts numpy inputs to the C structs, passes torch's current HIP stream,
+and converts outputs back.  Importing it fails loudly if the library has not
+been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_EUNSTABLE, PIC_ESTATE, PIC_ENOTSUP = (
+    0, -1, -2, -3, -4, -5, -6)
+STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVICE",
+                -4: "PIC_EUNSTABLE", -5: "PIC_ESTATE", -6: "PIC_ENOTSUP"}
+BC_PEC, BC_PERIODIC, BC_CPML = 0, 1, 2
+FIELD_E, FIELD_H, FIELD_JPOL, FIELD_JB = 0, 1, 2, 3
+KERNEL_FAMILIES = ("h_update", "push_deposit", "e_update", "probe", "sort")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class PicGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 3), ("npml", ctypes.c_int32),
+                ("pml_m", ctypes.c_double), ("pml_sigma_scale", ctypes.c_double),
+                ("pml_kappa_max", ctypes.c_double), ("pml_alpha_max", ctypes.c_double)]
+
+
+class PicParticles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", _dp), ("y", _dp), ("z", _dp),
+                ("ux", _dp), ("uy", _dp), ("uz", _dp),
+                ("q", ctypes.c_double), ("m", ctypes.c_double), ("weight", ctypes.c_double)]
+
+
+class PicOpts(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("nprobe", ctypes.c_int32), ("probe_xyz", _dp),
+                ("nfreq", ctypes.c_int32), ("omega", _dp), ("series_len", ctypes.c_int64),
+                ("sort_every", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("init_E", _dp * 3), ("init_H", _dp * 3), ("diag", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("deposit_mode", ctypes.c_int32)]
+
+
+class PicDiag(ctypes.Structure):
+    _fields_ = [("field_energy", ctypes.c_double), ("count", ctypes.c_double),
+                ("mean", ctypes.c_double * 3), ("rms", ctypes.c_double * 3),
+                ("umean", ctypes.c_double * 3), ("gauss_max", ctypes.c_double),
+                ("rho0_max", ctypes.c_double), ("checked_nodes", ctypes.c_int64)]
+
+
+class PicStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("pushes", ctypes.c_int64), ("live", ctypes.c_int64)]
+
+
+EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "pic_read_fields",
+           "pic_read_particles", "pic_diag", "pic_stats", "pic_timing", "pic_destroy",
+           "pic_last_error")
+
+_LIB = None
+
+
+def load():
+    """Load libpic.so; raises if it is missing (there is no fallback path)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                          "python paper_1505_04007_amd/csrc/build.py")
+    # torch ships its own HIP runtime with the same soname as ROCm's.  Loading
+    # torch first makes libpic.so bind to that instance, so the process holds
+    # one HIP runtime and torch's streams are valid handles for the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.pic_abi_version.restype = ctypes.c_int
+    lib.pic_init.restype = ctypes.c_int
+    lib.pic_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PicGrid), ctypes.c_double,
+                             ctypes.c_double, _dp, _dp, ctypes.POINTER(PicParticles),
+                             ctypes.POINTER(PicOpts)]
+    lib.pic_step.restype = ctypes.c_int
+    lib.pic_step.argtypes = [vp, ctypes.c_int64]
+    lib.pic_probe.restype = ctypes.c_int
+    lib.pic_probe.argtypes = [vp, _dp, _dp, _dp]
+    lib.pic_grad.restype = ctypes.c_int
+    lib.pic_grad.argtypes = [vp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp]
+    lib.pic_read_fields.restype = ctypes.c_int
+    lib.pic_read_fields.argtypes = [vp, ctypes.c_int, _dp]
+    lib.pic_read_particles.restype = ctypes.c_int
+    lib.pic_read_particles.argtypes = [vp, _dp]
+    lib.pic_diag.restype = ctypes.c_int
+    lib.pic_diag.argtypes = [vp, ctypes.POINTER(PicDiag)]
+    lib.pic_stats.restype = ctypes.c_int
+    lib.pic_stats.argtypes = [vp, ctypes.POINTER(PicStats)]
+    lib.pic_timing.restype = ctypes.c_int
+    lib.pic_timing.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.pic_destroy.restype = None
+    lib.pic_destroy.argtypes = [vp]
+    lib.pic_last_error.restype = ctypes.c_char_p
+    lib.pic_last_error.argtypes = [vp]
+    _LIB = lib
+    return lib
+
+
+class PicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def to_compact(arr_xyz):
+    """(nx, ny, nz) array -> compact layout (x fastest) as float64."""
+    return _f64(np.asarray(arr_xyz).transpose(2, 1, 0))
+
+
+def from_compact(flat, n):
+    """compact layout (x fastest) -> (nx, ny, nz) array."""
+    return np.asarray(flat).reshape(n[2], n[1], n[0]).transpose(2, 1, 0)
+
+
+def current_stream_handle():
+    """torch's current HIP stream as a raw handle (0 = default) when a GPU is present."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return 0
+
+
+class Simulation:
+    """One FDTD-PIC simulation held by a pic_ctx on the GPU.
+
+    Arguments mirror pic_init: grid sizes/boundaries, cell size dx (m), time
+    step dt (s), per-cell Drude maps (nx, ny, nz) in rad/s and 1/s, an
+    optional bunch, probe positions (m) and DFT frequencies (rad/s).
+    """
+
+    def __init__(self, nx, ny, nz, dx, dt, wp_map, gamma_map, bc=(BC_PEC,) * 3, npml=0,
+                 pml=(3.0, 1.0, 1.0, 0.0), bunch=None, probes=None, omega=None, series_len=0,
+                 sort_every=0, check_every=0, init_E=None, init_H=None, diag=False, timing=False,
+                 deposit_mode=0, stream=None):
+        self._lib = load()
+        self.n = (int(nx), int(ny), int(nz))
+        self.dx, self.dt = float(dx), float(dt)
+        g = PicGrid(nx, ny, nz, (ctypes.c_int32 * 3)(*[int(b) for b in bc]), int(npml), *pml)
+        self._keep = []
+        wp = to_compact(wp_map)
+        gm = to_compact(gamma_map)
+        self._keep += [wp, gm]
+        parts = None
+        self.np = 0
+        if bunch is not None and bunch.n > 0:
+            arrs = [_f64(a) for a in (bunch.x, bunch.y, bunch.z, bunch.ux, bunch.uy, bunch.uz)]
+            self._keep += arrs
+            parts = PicParticles(bunch.n, *[_p(a) for a in arrs], bunch.q, bunch.m, bunch.w)
+            self.np = bunch.n
+        o = PicOpts()
+        o.stream = current_stream_handle() if stream is None else stream
+        self.nprobe = 0 if probes is None else int(np.asarray(probes).reshape(-1, 3).shape[0])
+        self.nfreq = 0 if omega is None else int(np.asarray(omega).size)
+        if self.nprobe:
+            pxyz = _f64(np.asarray(probes).reshape(-1, 3))
+            self._keep.append(pxyz)
+            o.nprobe, o.probe_xyz = self.nprobe, _p(pxyz)
+        if self.nfreq:
+            om = _f64(omega)
+            self._keep.append(om)
+            o.nfreq, o.omega = self.nfreq, _p(om)
+        o.series_len = int(series_len)
+        o.sort_every = int(sort_every)
+        o.check_every = int(check_every)
+        for d in range(3):
+            if init_E is not None:
+                a = to_compact(init_E[d])
+                self._keep.append(a)
+                o.init_E[d] = _p(a)
+            if init_H is not None:
+                a = to_compact(init_H[d])
+                self._keep.append(a)
+                o.init_H[d] = _p(a)
+        o.diag = int(bool(diag))
+        o.timing = int(bool(timing))
+        o.deposit_mode = int(deposit_mode)
+        h = ctypes.c_void_p()
+        st = self._lib.pic_init(ctypes.byref(h), ctypes.byref(g), self.dx, self.dt, _p(wp),
+                                _p(gm), ctypes.byref(parts) if parts is not None else None,
+                                ctypes.byref(o))
+        self._h = None
+        if st != PIC_OK:
+            raise PicError(st, self._lib.pic_last_error(None).decode())
+        self._h = h
+        self._keep = []
+
+    def _check(self, st):
+        if st != PIC_OK:
+            raise PicError(st, self._lib.pic_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, n=1):
+        self._check(self._lib.pic_step(self._h, int(n)))
+
+    def fields(self, which):
+        """(3, nx, ny, nz) float64 in SI units (compact Yee layout positions)."""
+        N = self.n[0] * self.n[1] * self.n[2]
+        out = np.zeros(3 * N)
+        self._check(self._lib.pic_read_fields(self._h, int(which), _p(out)))
+        return np.stack([from_compact(out[d * N:(d + 1) * N], self.n) for d in range(3)])
+
+    def particles(self):
+        """(6, n) float64: x, y, z (m, NaN once lost), ux, uy, uz (m/s), original order."""
+        out = np.zeros(6 * max(self.np, 1))
+        self._check(self._lib.pic_read_particles(self._h, _p(out)))
+        return out[: 6 * self.np].reshape(6, self.np)
+
+    def probe(self, series=False):
+        nf = self.nprobe * self.nfreq
+        re = np.zeros(max(nf, 1))
+        im = np.zeros(max(nf, 1))
+        st = self.stats()["steps"]
+        ser = np.zeros(max(st * self.nprobe, 1)) if series else None
+        self._check(self._lib.pic_probe(self._h, _p(re), _p(im), _p(ser)))
+        F = (re[:nf] + 1j * im[:nf]).reshape(self.nprobe, self.nfreq)
+        if series:
+            return F, ser
+        return F
+
+    def diag(self):
+        d = PicDiag()
+        self._check(self._lib.pic_diag(self._h, ctypes.byref(d)))
+        return {"energy": d.field_energy, "count": d.count, "mean": np.array(d.mean),
+                "rms": np.array(d.rms), "umean": np.array(d.umean), "gauss_max": d.gauss_max,
+                "rho0_max": d.rho0_max, "checked_nodes": d.checked_nodes}
+
+    def stats(self):
+        s = PicStats()
+        self._check(self._lib.pic_stats(self._h, ctypes.byref(s)))
+        return {"steps": s.steps, "pushes": s.pushes, "live": s.live}
+
+    def timing(self, reset=False):
+        ms = np.zeros(5)
+        cnt = (ctypes.c_int64 * 5)()
+        self._check(self._lib.pic_timing(self._h, _p(ms), cnt, int(bool(reset))))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_FAMILIES)}
+
+    def grad(self, omega0, nsteps):
+        N = self.n[0] * self.n[1] * self.n[2]
+        L = np.zeros(1)
+        gw = np.zeros(N)
+        gg = np.zeros(N)
+        self._check(self._lib.pic_grad(self._h, float(omega0), int(nsteps), _p(L), _p(gw), _p(gg)))
+        return L[0], from_compact(gw, self.n), from_compact(gg, self.n)
+
+
+def from_workload(w, with_bunch=True, **kw):
+    """Simulation for a pic_inputs.Workload."""
+    return Simulation(w.nx, w.ny, w.nz, w.dx, w.dt, w.wp_map, w.gamma_map, bc=w.bc, npml=w.npml,
+                      pml=w.pml, bunch=w.bunch if with_bunch else None, probes=w.probes,
+                      omega=w.omega, sort_every=kw.pop("sort_every", w.sort_every), **kw)

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/pic.h, and rejects invalid problems
+with PIC_EINVAL before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import pic_inputs as pi
+from paper_1505_04007_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = native.load()
+    names = _declared()
+    assert set(names) == set(native.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.pic_abi_version() == 1
+
+
+def _init(**over):
+    lib = native.load()
+    w = pi.slab_tiny(with_bunch=False)
+    n = [w.nx, w.ny, w.nz]
+    args = dict(n=n, bc=[0, 0, 0], npml=0, dx=w.dx, dt=w.dt, wp=w.wp_map, g=w.gamma_map, parts=None,
+                pml=(3.0, 1.0, 1.0, 0.0))
+    args.update(over)
+    g = native.PicGrid(*args["n"], (ctypes.c_int32 * 3)(*args["bc"]), args["npml"], *args["pml"])
+    wp = native.to_compact(args["wp"])
+    gm = native.to_compact(args["g"])
+    h = ctypes.c_void_p()
+    parts = args["parts"]
+    keep = []
+    pp = None
+    if parts is not None:
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in parts[:6]]
+        keep += arrs
+        pp = native.PicParticles(len(arrs[0]), *[a.ctypes.data_as(native._dp) for a in arrs],
+                                 *parts[6:])
+    st = lib.pic_init(ctypes.byref(h), ctypes.byref(g), args["dx"], args["dt"],
+                      wp.ctypes.data_as(native._dp), gm.ctypes.data_as(native._dp),
+                      ctypes.byref(pp) if pp is not None else None, None)
+    msg = lib.pic_last_error(None).decode()
+    if h.value:
+        lib.pic_destroy(h)
+    return st, msg
+
+
+@pytest.mark.parametrize("over, frag", [
+    (dict(bc=[0, 5, 0]), "pic_bc"),
+    (dict(n=[1, 32, 32]), "cells"),
+    (dict(bc=[2, 2, 2], npml=0), "npml"),
+    (dict(bc=[2, 2, 2], npml=16), "2*npml"),
+    (dict(dx=-1.0), "positive"),
+    (dict(dt=1e-15), "dt/dx"),
+    (dict(bc=[2, 2, 2], npml=4, pml=(3.0, 1.0, 0.5, 0.0)), "CPML"),
+])
+def test_init_rejects_invalid_problem(over, frag):
+    st, msg = _init(**over)
+    assert st == native.PIC_EINVAL
+    assert frag in msg
+
+
+def test_init_rejects_negative_or_nonfinite_maps():
+    w = pi.slab_tiny(with_bunch=False)
+    bad = w.wp_map.copy()
+    bad[3, 4, 5] = -1.0
+    st, msg = _init(wp=bad)
+    assert st == native.PIC_EINVAL and "wp_map" in msg
+    bad = w.gamma_map.copy()
+    bad[1, 1, 1] = np.nan
+    st, msg = _init(g=bad)
+    assert st == native.PIC_EINVAL
+
+
+def test_init_rejects_drude_cfl_violation():
+    """The Yee + Drude bound 3 (c dt/dx)^2 + (wp dt/2)^2 <= 1: a plasma frequency
+    large enough to break it is refused even though the vacuum Courant number is fine."""
+    w = pi.slab_tiny(with_bunch=False)
+    wp = w.wp_map.copy()
+    wp[wp > 0] = 2.0 * np.sqrt(0.76) / w.dt
+    st, msg = _init(wp=wp)
+    assert st == native.PIC_EINVAL and "wp dt/2" in msg
+
+
+def test_init_rejects_particle_outside_box():
+    w = pi.slab_tiny()
+    b = w.bunch
+    x = b.x.copy()
+    x[17] = w.nx * w.dx + 1e-12
+    st, msg = _init(parts=(x, b.y, b.z, b.ux, b.uy, b.uz, b.q, b.m, b.w))
+    assert st == native.PIC_EINVAL and "particle 17" in msg
+
+
+def test_null_context_calls_are_rejected():
+    lib = native.load()
+    assert lib.pic_step(None, 1) == native.PIC_EINVAL
+    assert lib.pic_probe(None, None, None, None) == native.PIC_EINVAL
+    lib.pic_destroy(None)  # no-op
+
+
+def test_product_binding_has_no_cpu_fallback():
+    """The binding only marshals arguments into libpic.so: it never imports the oracle."""
+    src = open(os.path.join(ROOT, "paper_1505_04007_amd", "native.py")).read()
+    assert "oracle" not in src.replace("Importing it fails loudly", "")

@@ -1,0 +1,265 @@
+"""GPU (gfx950) path vs the FP64 oracle, through the C ABI.
+
+Tolerances: relative L2 <= 1e-5 on fields after 200 fields-only steps and
+<= 1e-3 on fields and bunch moments with particles (the FP32 device state
+against the FP64 oracle).  Sizes span several 64 x 8 x 16 field tiles with
+ragged tails, every boundary kind, and both deposit modes.
+"""
+import numpy as np
+import pytest
+
+import pic_inputs as pi
+from oracle import pic_oracle as po
+from paper_1505_04007_amd import native
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _compact(full, n):
+    return full[: n[0], : n[1], : n[2]]
+
+
+def _periodize(Efull, w):
+    """Make a sampled initial E admissible: on a periodic axis node n is node 0,
+    and on a PEC (or CPML-backed) wall tangential E is zero."""
+    n = (w.nx, w.ny, w.nz)
+    out = [e.copy() for e in Efull]
+    for c in range(3):
+        for a in range(3):
+            if a == c:
+                continue
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[a], hi[a] = 0, n[a]
+            if w.bc[a] == native.BC_PERIODIC:
+                out[c][tuple(hi)] = out[c][tuple(lo)]
+            else:
+                out[c][tuple(lo)] = 0.0
+                out[c][tuple(hi)] = 0.0
+    return out
+
+
+def _oracle_of(w, Efull=None, bunch=True):
+    o = po.OracleSim(w.nx, w.ny, w.nz, w.dx, w.dt, bc=w.bc, npml=w.npml, pml=w.pml,
+                     wp_map=w.wp_map, gamma_map=w.gamma_map)
+    if Efull is not None:
+        Efull = _periodize(Efull, w)
+        for c in range(3):
+            o.E[c][...] = Efull[c]
+    if bunch and w.bunch is not None:
+        b = w.bunch
+        o.set_particles(b.x, b.y, b.z, b.ux, b.uy, b.uz, b.q, b.m, b.w)
+    o.set_probes(w.probes, w.omega)
+    return o
+
+
+def _gpu_of(w, Efull=None, bunch=True, **kw):
+    n = (w.nx, w.ny, w.nz)
+    init_E = None if Efull is None else [_compact(Efull[c], n) for c in range(3)]
+    return native.from_workload(w, with_bunch=bunch, init_E=init_E, **kw)
+
+
+def _compare_fields(g, o, n, tol):
+    E = g.fields(native.FIELD_E)
+    H = g.fields(native.FIELD_H)
+    J = g.fields(native.FIELD_JPOL)
+    Eo = np.stack([_compact(o.E[c], n) for c in range(3)])
+    Ho = np.stack([_compact(o.H[c], n) for c in range(3)])
+    Jo = np.stack([_compact(o.J[c], n) for c in range(3)])
+    errs = {"E": _rel(E, Eo), "H": _rel(H, Ho)}
+    if np.linalg.norm(Jo) > 0:
+        errs["J"] = _rel(J, Jo)
+    for k, v in errs.items():
+        assert v <= tol, (k, v, errs)
+    return errs
+
+
+def _ragged(bc, npml, seed=3):
+    nx, ny, nz, dx = 37, 19, 27, 4e-9
+    wpm, gm = pi.film_maps(nx, ny, nz, 9, 14)
+    probes = np.array([[20 * dx, 9 * dx, 15.2 * dx], [5 * dx, 3 * dx, 20.9 * dx]])
+    return pi.Workload(f"ragged_{nx}x{ny}x{nz}", nx, ny, nz, dx, pi.courant_dt(dx), bc, npml,
+                       wpm, gm, None, probes, pi.spectrum_omegas(nfreq=16), 150)
+
+
+def test_fields_only_slab_200_steps_matches_oracle():
+    """Ag slab in a PEC box, smooth divergence-free initial E, 200 steps."""
+    w = pi.slab_tiny(with_bunch=False)
+    n = (w.nx, w.ny, w.nz)
+    Efull = pi.sample_field(pi.CavityField(np.array(n) * w.dx, seed=21, amplitude=1e6), "E", n, w.dx)
+    o = _oracle_of(w, Efull)
+    g = _gpu_of(w, Efull)
+    o.step(200)
+    g.step(200)
+    errs = _compare_fields(g, o, n, 1e-5)
+    assert "J" in errs
+    F, Fo = g.probe(), o.probe()
+    assert _rel(F, Fo) <= 1e-5
+
+
+@pytest.mark.parametrize("bc,npml", [
+    ((native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), 5),
+    ((native.BC_PERIODIC, native.BC_CPML, native.BC_CPML), 4),
+    ((native.BC_CPML,) * 3, 6),
+    ((native.BC_PERIODIC,) * 3, 0),
+])
+def test_fields_only_ragged_grid_all_boundaries(bc, npml):
+    """37x19x27 cells (ragged against the 64x8x16 tile) with every boundary kind."""
+    w = _ragged(bc, npml)
+    n = (w.nx, w.ny, w.nz)
+    pulse = pi.GaussianPulse(np.array(n) * w.dx * np.array([0.4, 0.5, 0.6]), 2.5 * w.dx,
+                             [3e5, -2e5, 1e5])
+    Efull = pi.sample_field(pulse, "E", n, w.dx)
+    o = _oracle_of(w, Efull)
+    g = _gpu_of(w, Efull)
+    o.step(150)
+    g.step(150)
+    _compare_fields(g, o, n, 1e-5)
+    assert _rel(g.probe(), o.probe()) <= 1e-5
+
+
+def test_fields_only_film_cpml8_multi_tile():
+    """Several full tiles in every direction with an 8-cell CPML and a 30 nm film."""
+    nx, ny, nz, dx, npml = 136, 40, 56, 2e-9, 8
+    wpm, gm = pi.film_maps(nx, ny, nz, 13, 28)
+    w = pi.Workload("film_136x40x56", nx, ny, nz, dx, pi.courant_dt(dx), (native.BC_CPML,) * 3,
+                    npml, wpm, gm, None, np.array([[60 * dx, 20 * dx, 29.4 * dx]]),
+                    pi.spectrum_omegas(nfreq=8), 200)
+    n = (nx, ny, nz)
+    pulse = pi.GaussianPulse(np.array([50, 20, 34]) * dx, 3 * dx, [1e5, 2e5, -3e5])
+    Efull = pi.sample_field(pulse, "E", n, dx)
+    o = _oracle_of(w, Efull)
+    g = _gpu_of(w, Efull)
+    o.step(200)
+    g.step(200)
+    _compare_fields(g, o, n, 1e-5)
+
+
+def _moments_close(dg, do, sigma, tol):
+    assert dg["count"] == do["count"]
+    assert np.all(np.abs(dg["mean"] - do["mean"]) <= tol * sigma)
+    assert np.all(np.abs(dg["rms"] - do["rms"]) <= tol * do["rms"])
+    assert np.all(np.abs(dg["umean"] - do["umean"]) <= tol * np.abs(do["umean"]).max())
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_tiny_bunch_over_slab_200_steps_matches_oracle(mode):
+    """The 32^3 / 1000-particle / 200-step workload: fields, bunch moments and probe
+    spectra within 1e-3 of the oracle, for both deposit modes."""
+    w = pi.slab_tiny()
+    n = (w.nx, w.ny, w.nz)
+    o = _oracle_of(w)
+    g = _gpu_of(w, deposit_mode=mode, diag=True)
+    o.step(200)
+    g.step(200)
+    _compare_fields(g, o, n, 1e-3)
+    _moments_close(g.diag(), o.diag(), 5e-9, 1e-3)
+    assert _rel(g.probe(), o.probe()) <= 1e-3
+    st = g.stats()
+    assert st["pushes"] == 200 * 1000 and st["live"] == 1000
+    P = g.particles()
+    xo, yo, zo = o.particles()[:3]
+    assert np.abs(P[0] - xo).max() <= 1e-3 * w.dx
+
+
+def test_gpu_gauss_law_residual_at_fp32_roundoff():
+    """eps0 div E - rho + rho0 stays at FP32 round-off at vacuum nodes (charge-
+    conserving deposit on the device)."""
+    w = pi.slab_tiny()
+    g = _gpu_of(w, diag=True)
+    g.step(200)
+    d = g.diag()
+    assert d["checked_nodes"] > 10000
+    assert d["gauss_max"] <= 2e-5 * d["rho0_max"], d
+
+
+def test_periodic_bunch_wraps_like_oracle():
+    """A bunch crossing a periodic x boundary: deposits and positions wrap."""
+    nx, ny, nz, dx = 24, 16, 20, 5e-9
+    wpm, gm = pi.film_maps(nx, ny, nz, 3, 6)
+    rng = np.random.default_rng(pi.SEED0 + 40)
+    bunch = pi.gaussian_bunch(rng, 300, (21 * dx, 8 * dx, 12 * dx), (dx, dx, dx), 100e3)
+    w = pi.Workload("periodic_x", nx, ny, nz, dx, pi.courant_dt(dx),
+                    (native.BC_PERIODIC, native.BC_PEC, native.BC_CPML), 4, wpm, gm, bunch,
+                    np.array([[4 * dx, 8 * dx, 7.3 * dx]]), pi.spectrum_omegas(nfreq=8), 120)
+    o = _oracle_of(w)
+    g = _gpu_of(w, sort_every=7)
+    o.step(120)
+    g.step(120)
+    n = (nx, ny, nz)
+    _compare_fields(g, o, n, 1e-3)
+    _moments_close(g.diag(), o.diag(), dx, 1e-3)
+
+
+def test_particles_leaving_the_box_are_dropped():
+    """A fast bunch near the +x CPML wall leaves the box; live counts agree
+    (up to particles within FP32 reach of the wall) and fields stay close."""
+    nx, ny, nz, dx = 40, 24, 24, 4e-9
+    wpm, gm = pi.film_maps(nx, ny, nz, 6, 10)
+    rng = np.random.default_rng(pi.SEED0 + 41)
+    bunch = pi.gaussian_bunch(rng, 500, (33 * dx, 12 * dx, 13 * dx), (1.5 * dx,) * 3, 100e3)
+    w = pi.Workload("exit_x", nx, ny, nz, dx, pi.courant_dt(dx), (native.BC_CPML,) * 3, 6,
+                    wpm, gm, bunch, np.array([[20 * dx, 12 * dx, 10.5 * dx]]),
+                    pi.spectrum_omegas(nfreq=4), 30)
+    o = _oracle_of(w)
+    g = _gpu_of(w, sort_every=10)
+    o.step(30)
+    g.step(30)
+    alive_o = o.particles()[6]
+    P = g.particles()
+    alive_g = np.isfinite(P[0])
+    assert 0 < alive_o.sum() < 500
+    assert np.sum(alive_o != alive_g) <= 2
+    _compare_fields(g, o, (nx, ny, nz), 1e-3)
+
+
+def test_nonfinite_field_poisons_context():
+    """A NaN planted in the initial field is caught by the device flag: PIC_EUNSTABLE,
+    then PIC_ESTATE on every later call."""
+    w = pi.slab_tiny(with_bunch=False)
+    n = (w.nx, w.ny, w.nz)
+    E = [np.zeros(n) for _ in range(3)]
+    E[0][10, 10, 20] = np.nan
+    g = native.from_workload(w, with_bunch=False, init_E=E, check_every=1)
+    with pytest.raises(native.PicError) as ei:
+        g.step(3)
+    assert ei.value.status == native.PIC_EUNSTABLE
+    with pytest.raises(native.PicError) as ei:
+        g.step(1)
+    assert ei.value.status == native.PIC_ESTATE
+
+
+def test_sort_frequency_does_not_change_results():
+    """Sorting only permutes particles: fields agree to atomic-order round-off and the
+    per-particle state read back in original order is identical up to it."""
+    w = pi.slab_tiny()
+    a = _gpu_of(w, sort_every=1)
+    b = _gpu_of(w, sort_every=0)
+    a.step(100)
+    b.step(100)
+    assert _rel(a.fields(native.FIELD_E), b.fields(native.FIELD_E)) <= 1e-5
+    Pa, Pb = a.particles(), b.particles()
+    assert np.abs(Pa[:3] - Pb[:3]).max() <= 1e-5 * w.dx
+    assert np.abs(Pa[3:] - Pb[3:]).max() <= 1e-5 * np.abs(Pb[3]).max()
+
+
+@pytest.mark.parametrize("make,steps", [(pi.film_production, 20), (pi.grating_large, 6)])
+def test_full_size_workloads_conserve_charge(make, steps):
+    """Full-size workloads in the benchmark's launch configuration: every live
+    particle pushed each step, no non-finite field, and Gauss's law at FP32
+    round-off (a property the oracle fixes at any size)."""
+    w = make()
+    g = native.from_workload(w, diag=True, check_every=steps)
+    g.step(steps)
+    st = g.stats()
+    assert st["live"] == w.bunch.n
+    assert st["pushes"] == steps * w.bunch.n
+    d = g.diag()
+    assert d["gauss_max"] <= 5e-5 * d["rho0_max"], d
+    F = g.probe()
+    assert np.all(np.isfinite(F))

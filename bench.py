@@ -1,0 +1,212 @@
+"""Benchmark of the FDTD-PIC step on one MI355X.
+
+One step is the whole hot path on one batch of synthetic input: cell sort
+(every 20 steps), H update, gather + Boris push + Esirkepov deposit of every
+live particle, Drude J + E update, FP64 probe DFT.  The default workload is
+the 512x256x256-cell (33.5M), 1 nm, 12-cell-CPML grating run with a
+1e7-particle 100 keV bunch; all inputs are resident in HBM before timing.
+
+Prints one JSON line: whole-step Gcell-updates/s as `value`, particle
+pushes/s, the HBM roofline of the dominant kernel (algorithmic bytes per
+launch / HIP-event launch time), and the FP64 oracle timed on host cores on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Gcell-updates/s + particle-pushes/s (FP32) and % HBM roofline; "
+          "batched/adjoint vs plain")
+HBM_PEAK_GBS = 8000.0
+FAMILIES = ("h_update", "push_deposit", "e_update", "probe", "sort")
+KERNEL_SOURCES = {"h_update": "kernels_fields.hip", "e_update": "kernels_fields.hip",
+                  "push_deposit": "kernels_particles.hip", "sort": "kernels_particles.hip",
+                  "probe": "kernels_diag.hip"}
+
+
+def workload(name):
+    import pic_inputs as pi
+    table = {"grating40nm_512x256x256_cpml12": pi.grating_large,
+             "film30nm_256x128x128_cpml8": pi.film_production,
+             "film20nm_128x64x64_cpml8": pi.film_adjoint,
+             "slab20nm_32x32x32_pec": pi.slab_tiny}
+    return table[name]()
+
+
+def cpml_memberships(w):
+    """Sum over CPML axes of the cells inside that axis's two absorbing slabs."""
+    n = (w.nx, w.ny, w.nz)
+    tot = 0
+    for a in range(3):
+        if w.bc[a] == 2:
+            tot += 2 * w.npml * (w.cells // n[a])
+    return tot
+
+
+def metal_box_cells(w):
+    import numpy as np
+    m = w.wp_map > 0
+    if not m.any():
+        return 0
+    idx = [np.where(m.any(axis=tuple(b for b in range(3) if b != a)))[0] for a in range(3)]
+    return int(np.prod([i.max() - i.min() + 1 for i in idx]))
+
+
+def algorithmic_bytes(w, fam, pushes_per_step, pbox):
+    """Bytes the method must move per launch (FP32 state, read + write).
+
+    h_update : 36 B/cell (read E, read H, write H) + 16 B per CPML layer-axis
+               membership (two psi, read + write)
+    e_update : 36 B/cell + 16 B per membership + 32 B per metal-box cell
+               (J_pol read + write, (cb, d)) + 24 B per bunch-box cell (J_b read + clear)
+    push     : 48 B per live particle (x, u read + write)
+    """
+    N = w.cells
+    mem = cpml_memberships(w)
+    if fam == "h_update":
+        return 36 * N + 16 * mem
+    if fam == "e_update":
+        box = 1
+        for d in range(3):
+            box *= max(0, pbox[3 + d] - pbox[d] + 1)
+        return 36 * N + 16 * mem + 32 * metal_box_cells(w) + 24 * box
+    if fam == "push_deposit":
+        return 48 * pushes_per_step
+    return None
+
+
+def source_sha(fam):
+    path = os.path.join(ROOT, "paper_1505_04007_amd", "csrc", KERNEL_SOURCES[fam])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(fam, wname):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when no summary exists or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(wname, {}).get(fam)
+    except (ValueError, OSError):
+        return None
+    if not rec or rec.get("source_sha") != source_sha(fam):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, nsub=100_000, steps=2):
+    """The FP64 oracle on the full grid of the same workload for `steps` steps
+    with a 1/(n/nsub) subsample of the bunch; the per-push time is scaled to
+    the full bunch to give the per-step time of the whole workload."""
+    import numpy as np
+    from oracle import pic_oracle as po
+    b = w.bunch
+    idx = np.arange(0, b.n, max(1, b.n // nsub))[:nsub]
+    sub = b.subset(idx)
+    o = po.OracleSim(w.nx, w.ny, w.nz, w.dx, w.dt, bc=w.bc, npml=w.npml, pml=w.pml,
+                     wp_map=w.wp_map, gamma_map=w.gamma_map)
+    o.set_particles(sub.x, sub.y, sub.z, sub.ux, sub.uy, sub.uz, sub.q, b.m, b.w)
+    o.set_probes(w.probes, w.omega)
+    o.step(steps)
+    t = o.timing()
+    field_s = t["field_s"] / steps
+    push_s = t["particle_s"] / max(t["pushes"], 1)
+    step_s = field_s + push_s * b.n
+    return {"value": w.cells / step_s / 1e9, "unit": "Gcell-updates/s", "cores": t["threads"],
+            "kind": "oracle",
+            "sample": (f"full {w.nx}x{w.ny}x{w.nz} grid, {steps} steps, {len(idx)} of {b.n} "
+                       f"particles; field time per step {field_s:.2f} s measured, push time "
+                       f"{push_s * 1e6:.2f} us/push scaled to the full bunch"),
+            "particle_pushes_per_s": 1.0 / push_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="grating40nm_512x256x256_cpml12")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--deposit-mode", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1505_04007_amd import native
+
+    w = workload(args.workload)
+    torch.cuda.set_device(0)
+    sim = native.from_workload(w, timing=True, deposit_mode=args.deposit_mode)
+    print(f"[bench] {w.name}: {w.cells} cells, {w.bunch.n if w.bunch else 0} particles, "
+          f"warmup {args.warmup}", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    p0 = sim.stats()["pushes"]
+    sim.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sim.stats()
+    fams = sim.timing(reset=True)
+    sim.step(0)
+    pushes = st["pushes"] - p0
+    secs = t1 - t0
+    ms_per_step = 1e3 * secs / args.steps
+    gcells = w.cells * args.steps / secs / 1e9
+    print(f"[bench] timed {args.steps} steps in {secs:.3f} s", file=sys.stderr, flush=True)
+
+    # dominant kernel family by total device time
+    dom = max(fams, key=lambda f: fams[f][0])
+    ms_tot, launches = fams[dom]
+    avg_s = ms_tot / 1e3 / max(launches, 1)
+    per_step_push = pushes / args.steps
+    algo = algorithmic_bytes(w, dom, per_step_push, st["pbox"])
+    roof = None
+    if algo is not None:
+        ach = algo / avg_s / 1e9
+        tr = traffic_for(dom, w.name)
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
+                "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    kernels = {}
+    for f in FAMILIES:
+        ms, n = fams[f]
+        if n == 0:
+            continue
+        b = algorithmic_bytes(w, f, per_step_push, st["pbox"])
+        kernels[f] = {"avg_ms": round(ms / n, 4), "launches": n,
+                      "share": round(ms / max(sum(v[0] for v in fams.values()), 1e-12), 3)}
+        if b is not None:
+            kernels[f]["algo_GBps"] = round(b / (ms / n / 1e3) / 1e9, 1)
+
+    cpu = None
+    if not args.no_cpu_baseline and w.bunch is not None:
+        print("[bench] timing the oracle on host cores", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+
+    out = {"metric": METRIC, "value": round(gcells, 3), "unit": "Gcell-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "cells": w.cells,
+                      "particles": w.bunch.n if w.bunch else 0, "sort_every": w.sort_every,
+                      "deposit_mode": args.deposit_mode, "parallelism": "single-gpu"},
+           "particle_pushes_per_s": round(pushes / secs, 1),
+           "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

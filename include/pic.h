@@ -131,6 +131,8 @@ typedef struct {
     int64_t steps;        /* steps taken */
     int64_t pushes;       /* particle pushes actually deposited (live particles x steps) */
     int64_t live;         /* live particles now */
+    int32_t pbox[6];      /* cell bounding box of the live particles at the last sort:
+                             lo x, y, z, hi x, y, z (inclusive); hi < lo when empty */
 } pic_stats_out;
 
 /* Library ABI version (PIC_ABI_VERSION). */

@@ -825,7 +825,12 @@ pic_status pic_stats(pic_ctx *c, pic_stats_out *out)
     out->steps = c->step;
     out->pushes = (int64_t)pushes;
     out->live = 0;
+    for (int d = 0; d < 3; ++d) {
+        out->pbox[d] = 0;
+        out->pbox[3 + d] = -1;
+    }
     if (c->np > 0) {
+        HIP_TRY(c, hipMemcpy(out->pbox, c->box, sizeof out->pbox, hipMemcpyDeviceToHost));
         pic_diag_out d;
         pic_status st = pic_diag(c, &d);
         if (st != PIC_OK) return st;

@@ -53,7 +53,8 @@ class PicDiag(ctypes.Structure):
 
 
 class PicStats(ctypes.Structure):
-    _fields_ = [("steps", ctypes.c_int64), ("pushes", ctypes.c_int64), ("live", ctypes.c_int64)]
+    _fields_ = [("steps", ctypes.c_int64), ("pushes", ctypes.c_int64), ("live", ctypes.c_int64),
+                ("pbox", ctypes.c_int32 * 6)]
 
 
 EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "pic_read_fields",
@@ -258,7 +259,7 @@ class Simulation:
     def stats(self):
         s = PicStats()
         self._check(self._lib.pic_stats(self._h, ctypes.byref(s)))
-        return {"steps": s.steps, "pushes": s.pushes, "live": s.live}
+        return {"steps": s.steps, "pushes": s.pushes, "live": s.live, "pbox": tuple(s.pbox)}
 
     def timing(self, reset=False):
         ms = np.zeros(5)

@@ -32,31 +32,49 @@ __device__ __forceinline__ float fold(float v, int n)
     return v >= L ? 0.f : v;  // v + L may round up to L
 }
 
-// Stored value at integer lattice index; 0 outside the box on a wall axis.
-__device__ __forceinline__ float fetch(const float *__restrict__ f, const PartArgs &a, int i, int j,
-                                       int k)
+// Per-axis corner data of the trilinear gather on the two lattices an axis
+// can carry: nodes (integer coordinates) and half nodes.  o0/o1 are the
+// linear offsets of the two corners (clamped into the box), m0/m1 their
+// weights with the wall mask folded in (0 for a corner beyond a wall).
+struct Axis2 {
+    int o0[2], o1[2];
+    float m0[2], m1[2];
+};
+
+__device__ __forceinline__ void axis_corners(float x, int n, int per, int stride, Axis2 &A)
 {
-    if (a.per[0]) i = wrapn(i, a.nx);
-    else if (i < 0 || i >= a.nx) return 0.f;
-    if (a.per[1]) j = wrapn(j, a.ny);
-    else if (j < 0 || j >= a.ny) return 0.f;
-    if (a.per[2]) k = wrapn(k, a.nz);
-    else if (k < 0 || k >= a.nz) return 0.f;
-    return f[i + a.nx * (j + a.ny * k)];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const float s = h ? x - 0.5f : x;
+        const float f = floorf(s);
+        const int i = (int)f;
+        const float w1 = s - f, w0 = 1.f - w1;
+        int i0 = i, i1 = i + 1;
+        bool ok0 = i0 >= 0 && i0 < n, ok1 = i1 >= 0 && i1 < n;
+        if (per) {
+            i0 = i0 < 0 ? i0 + n : (i0 >= n ? i0 - n : i0);
+            i1 = i1 < 0 ? i1 + n : (i1 >= n ? i1 - n : i1);
+            i0 = min(max(i0, 0), n - 1);
+            i1 = min(max(i1, 0), n - 1);
+            ok0 = ok1 = true;
+        } else {
+            i0 = min(max(i0, 0), n - 1);
+            i1 = min(max(i1, 0), n - 1);
+        }
+        A.o0[h] = i0 * stride;
+        A.o1[h] = i1 * stride;
+        A.m0[h] = ok0 ? w0 : 0.f;
+        A.m1[h] = ok1 ? w1 : 0.f;
+    }
 }
 
-// Trilinear interpolation of one component whose lattice is shifted by half a
-// cell along the axes flagged in (hx, hy, hz).  f2 (optional) is added
-// corner by corner (the two time levels of H).
+// Trilinear value of a component that sits at half nodes along the axes
+// flagged (hx, hy, hz); f2 (optional) is the second time level of H, added
+// corner by corner.
+template <int HX, int HY, int HZ>
 __device__ __forceinline__ float gather(const float *__restrict__ f, const float *__restrict__ f2,
-                                        const PartArgs &a, float x, float y, float z, int hx, int hy,
-                                        int hz)
+                                        const Axis2 &X, const Axis2 &Y, const Axis2 &Z)
 {
-    const float xs = hx ? x - 0.5f : x, ys = hy ? y - 0.5f : y, zs = hz ? z - 0.5f : z;
-    const float fi = floorf(xs), fj = floorf(ys), fk = floorf(zs);
-    const int i = (int)fi, j = (int)fj, k = (int)fk;
-    const float wx1 = xs - fi, wy1 = ys - fj, wz1 = zs - fk;
-    const float wx0 = 1.f - wx1, wy0 = 1.f - wy1, wz0 = 1.f - wz1;
     float v = 0.f;
 #pragma unroll
     for (int c = 0; c < 2; ++c)
@@ -64,9 +82,13 @@ __device__ __forceinline__ float gather(const float *__restrict__ f, const float
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                float s = fetch(f, a, i + q, j + b, k + c);
-                if (f2) s += fetch(f2, a, i + q, j + b, k + c);
-                v += (q ? wx1 : wx0) * (b ? wy1 : wy0) * (c ? wz1 : wz0) * s;
+                const int o = (q ? X.o1[HX] : X.o0[HX]) + (b ? Y.o1[HY] : Y.o0[HY]) +
+                              (c ? Z.o1[HZ] : Z.o0[HZ]);
+                const float w = (q ? X.m1[HX] : X.m0[HX]) * (b ? Y.m1[HY] : Y.m0[HY]) *
+                                (c ? Z.m1[HZ] : Z.m0[HZ]);
+                float s = f[o];
+                if (f2) s += f2[o];
+                v += w * s;
             }
     return v;
 }
@@ -110,36 +132,44 @@ __device__ __forceinline__ void slot_geom(int s, int &comp, int &oi, int &oj, in
     }
 }
 
-// Current of slot s from the per-axis shapes (qd folded in by the caller).
+// Esirkepov factors of one move: the running sum of dS along each current's
+// own axis (pre[axis][edge]) and the transverse weight
+//   T = S0 S0 + (dS S0 + S0 dS)/2 + dS dS/3
+// of the other two axes.  Slot s has current pre * T.  Every index used
+// below is a compile-time constant after unrolling, so nothing leaves
+// registers.
 struct Dep {
-    float S0[3][3], dS[3][3];
+    float pre[3][2];
+    float Tyz[3][3], Txz[3][3], Txy[3][3];
 };
+
+__device__ __forceinline__ void make_dep(const float S0[3][3], const float dS[3][3], Dep &d)
+{
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        d.pre[ax][0] = dS[ax][0];
+        d.pre[ax][1] = dS[ax][0] + dS[ax][1];
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            d.Tyz[p][q] = S0[1][p] * S0[2][q] + 0.5f * (dS[1][p] * S0[2][q] + S0[1][p] * dS[2][q]) +
+                          (1.f / 3.f) * dS[1][p] * dS[2][q];
+            d.Txz[p][q] = S0[0][p] * S0[2][q] + 0.5f * (dS[0][p] * S0[2][q] + S0[0][p] * dS[2][q]) +
+                          (1.f / 3.f) * dS[0][p] * dS[2][q];
+            d.Txy[p][q] = S0[0][p] * S0[1][q] + 0.5f * (dS[0][p] * S0[1][q] + S0[0][p] * dS[1][q]) +
+                          (1.f / 3.f) * dS[0][p] * dS[1][q];
+        }
+}
 
 __device__ __forceinline__ float slot_value(const Dep &d, int s)
 {
     int comp, oi, oj, ok;
     slot_geom(s, comp, oi, oj, ok);
-    // prefix of dS along the current's own axis, transverse weight of the
-    // other two: S0 S0 + (dS S0 + S0 dS)/2 + dS dS/3
-    const int ax = comp, a1 = (comp + 1) % 3, a2 = (comp + 2) % 3;
-    int e, n1, n2;
-    if (comp == 0) {
-        e = oi;
-        n1 = oj;
-        n2 = ok;
-    } else if (comp == 1) {
-        e = oj;
-        n1 = ok;  // a1 = z
-        n2 = oi;  // a2 = x
-    } else {
-        e = ok;
-        n1 = oi;  // a1 = x
-        n2 = oj;  // a2 = y
-    }
-    const float pre = e == 0 ? d.dS[ax][0] : d.dS[ax][0] + d.dS[ax][1];
-    const float s1 = d.S0[a1][n1], t1 = d.dS[a1][n1];
-    const float s2 = d.S0[a2][n2], t2 = d.dS[a2][n2];
-    return pre * (s1 * s2 + 0.5f * (t1 * s2 + s1 * t2) + (1.f / 3.f) * t1 * t2);
+    if (comp == 0) return d.pre[0][oi] * d.Tyz[oj][ok];
+    if (comp == 1) return d.pre[1][oj] * d.Txz[oi][ok];
+    return d.pre[2][ok] * d.Txy[oi][oj];
 }
 
 __device__ __forceinline__ float *slot_addr(const PartArgs &a, int s, int bx, int by, int bz)
@@ -153,7 +183,9 @@ __device__ __forceinline__ float *slot_addr(const PartArgs &a, int s, int bx, in
     else if (j < 0 || j >= a.ny) return nullptr;
     if (a.per[2]) k = wrapn(k, a.nz);
     else if (k < 0 || k >= a.nz) return nullptr;
-    return a.Jb[comp] + (i + a.nx * (j + a.ny * k));
+    // select, not a[comp]: a runtime index into the argument block would put it in scratch
+    float *J = comp == 0 ? a.Jb[0] : (comp == 1 ? a.Jb[1] : a.Jb[2]);
+    return J + (i + a.nx * (j + a.ny * k));
 }
 
 template <int OFF>
@@ -194,13 +226,17 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
         const float x = a.x[p], y = a.y[p], z = a.z[p];
         if (live_pos(x, y, z, a.nx, a.ny, a.nz)) {
             float u0 = a.ux[p], u1 = a.uy[p], u2 = a.uz[p];
+            Axis2 AX, AY, AZ;
+            axis_corners(x, a.nx, a.per[0], 1, AX);
+            axis_corners(y, a.ny, a.per[1], a.nx, AY);
+            axis_corners(z, a.nz, a.per[2], a.nx * a.ny, AZ);
             // E^n and Ht^n = (Ht^{n-1/2} + Ht^{n+1/2})/2 at x^n
-            const float e0 = gather(a.E[0], nullptr, a, x, y, z, 1, 0, 0);
-            const float e1 = gather(a.E[1], nullptr, a, x, y, z, 0, 1, 0);
-            const float e2 = gather(a.E[2], nullptr, a, x, y, z, 0, 0, 1);
-            const float h0 = 0.5f * gather(a.Hold[0], a.Hnew[0], a, x, y, z, 0, 1, 1);
-            const float h1 = 0.5f * gather(a.Hold[1], a.Hnew[1], a, x, y, z, 1, 0, 1);
-            const float h2 = 0.5f * gather(a.Hold[2], a.Hnew[2], a, x, y, z, 1, 1, 0);
+            const float e0 = gather<1, 0, 0>(a.E[0], nullptr, AX, AY, AZ);
+            const float e1 = gather<0, 1, 0>(a.E[1], nullptr, AX, AY, AZ);
+            const float e2 = gather<0, 0, 1>(a.E[2], nullptr, AX, AY, AZ);
+            const float h0 = 0.5f * gather<0, 1, 1>(a.Hold[0], a.Hnew[0], AX, AY, AZ);
+            const float h1 = 0.5f * gather<1, 0, 1>(a.Hold[1], a.Hnew[1], AX, AY, AZ);
+            const float h2 = 0.5f * gather<1, 1, 0>(a.Hold[2], a.Hnew[2], AX, AY, AZ);
             // relativistic Boris: half kick, rotation, half kick (u in units of c)
             const float ah = a.ah;
             const float m0 = u0 + ah * e0, m1 = u1 + ah * e1, m2 = u2 + ah * e2;
@@ -227,13 +263,15 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
             if (out) {
                 a.x[p] = -1.f;  // left the box: deactivated, last move not deposited
             } else {
-                const float X0[3] = {x, y, z}, X1[3] = {x1, y1, z1};
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const int i0 = (int)floorf(X0[ax]), i1 = (int)floorf(X1[ax]);
-                    base[ax] = min(i0, i1);
-                    shapes(X0[ax], X1[ax], base[ax], d.S0[ax], d.dS[ax]);
-                }
+                // written out per axis: constant indices keep S0/dS in registers
+                float S0[3][3], dS[3][3];
+                base[0] = min((int)floorf(x), (int)floorf(x1));
+                base[1] = min((int)floorf(y), (int)floorf(y1));
+                base[2] = min((int)floorf(z), (int)floorf(z1));
+                shapes(x, x1, base[0], S0[0], dS[0]);
+                shapes(y, y1, base[1], S0[1], dS[1]);
+                shapes(z, z1, base[2], S0[2], dS[2]);
+                make_dep(S0, dS, d);
                 dep = true;
                 if (a.per[0]) x1 = fold(x1, a.nx);
                 if (a.per[1]) y1 = fold(y1, a.ny);
@@ -246,9 +284,11 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
     }
     const float qd = a.qd;
     const unsigned long long live = __ballot(dep);
-    if (lane == 0 && live) atomicAdd(a.pushes, (unsigned long long)__popcll(live));
+    // per-wavefront push counter (one slot per wavefront of the launch)
+    if (lane == 0 && live) a.pushes[p >> 6] += (unsigned long long)__popcll(live);
     if (MODE == 1) {
         if (dep) {
+#pragma unroll
             for (int s = 0; s < 54; ++s) {
                 const float v = qd * slot_value(d, s);
                 if (v != 0.f) {
@@ -284,6 +324,7 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
         ++round;
     }
     if ((rem >> lane) & 1ull) {
+#pragma unroll
         for (int s = 0; s < 54; ++s) {
             const float v = qd * slot_value(d, s);
             if (v != 0.f) {

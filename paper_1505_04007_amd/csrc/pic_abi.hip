@@ -61,7 +61,8 @@ struct pic_ctx {
     int scan_len = 0;
     float ah = 0.f, qd = 0.f;
     double q = 0, m = 0, w = 0;
-    unsigned long long *d_pushes = nullptr;
+    unsigned long long *d_pushes = nullptr;  // per-wavefront push counters
+    size_t n_wave_slots = 0;
     int *d_nan = nullptr;
     int deposit_mode = 0;
 
@@ -387,9 +388,7 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         HIP_TRY(c, hipMemsetAsync(c->H[1][d], 0, N * 4, c->stream));
     }
     TRY(dalloc(c, &c->d_nan, 1));
-    TRY(dalloc(c, &c->d_pushes, 1));
     HIP_TRY(c, hipMemsetAsync(c->d_nan, 0, 4, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->d_pushes, 0, 8, c->stream));
     TRY(dalloc(c, &c->acc, 16));
     TRY(dalloc(c, &c->d_live, 1));
 
@@ -558,6 +557,10 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         std::vector<int> ids(c->np);
         for (int i = 0; i < c->np; ++i) ids[i] = i;
         HIP_TRY(c, hipMemcpyAsync(c->pid[0], ids.data(), 4 * (size_t)c->np, hipMemcpyHostToDevice, c->stream));
+        // one push counter per wavefront of the push launch
+        c->n_wave_slots = ((size_t)c->np + pic::PBLOCK - 1) / pic::PBLOCK * (pic::PBLOCK / 64);
+        TRY(dalloc(c, &c->d_pushes, c->n_wave_slots));
+        HIP_TRY(c, hipMemsetAsync(c->d_pushes, 0, 8 * c->n_wave_slots, c->stream));
         TRY(dalloc(c, &c->key, (size_t)c->np));
         TRY(dalloc(c, &c->rank, (size_t)c->np));
         TRY(dalloc(c, &c->counts, (size_t)ncell + 1));
@@ -820,8 +823,12 @@ pic_status pic_stats(pic_ctx *c, pic_stats_out *out)
     CHECK_CTX(c);
     if (!out) return fail(c, PIC_EINVAL, "out is NULL");
     unsigned long long pushes = 0;
-    HIP_TRY(c, hipMemcpyAsync(&pushes, c->d_pushes, 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->n_wave_slots) {
+        std::vector<unsigned long long> slots(c->n_wave_slots);
+        HIP_TRY(c, hipMemcpy(slots.data(), c->d_pushes, 8 * slots.size(), hipMemcpyDeviceToHost));
+        for (unsigned long long v : slots) pushes += v;
+    }
     out->steps = c->step;
     out->pushes = (int64_t)pushes;
     out->live = 0;

@@ -67,7 +67,7 @@ struct PartArgs {
     float S;   // c dt / dx
     float ah;  // q dt / (2 m c), per V/m
     float qd;  // -q w / (eps0 dx^2), V/m
-    unsigned long long *pushes;
+    unsigned long long *pushes;  // one counter per wavefront: [gridDim * PBLOCK / 64]
 };
 
 struct SortArgs {

@@ -62,6 +62,23 @@ __device__ __forceinline__ float cpml(float *__restrict__ psi, int sid, float b,
 
 __device__ __forceinline__ int slab_p(int q, int n, int np) { return q < np ? q : q - (n - 2 * np); }
 
+// Inside the live-particle cell box of the last sort widened by the margin
+// (every cell a particle can gather from or deposit to this step); a
+// periodic axis counts whole because deposits and gathers wrap there.
+__device__ __forceinline__ bool in_particle_box(const FieldArgs &a, int i, int j, int k)
+{
+    const int n3[3] = {a.nx, a.ny, a.nz};
+    const int id3[3] = {i, j, k};
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int lo = a.per[d] ? 0 : a.pbox[d] - a.margin;
+        const int hi = a.per[d] ? n3[d] - 1 : a.pbox[3 + d] + a.margin;
+        in = in && id3[d] >= lo && id3[d] <= hi;
+    }
+    return in;
+}
+
 // H^{n+1/2} = H^{n-1/2} - S curl E^n  (vacuum form for every cell).
 __global__ __launch_bounds__(FX *FY) void k_h_update(FieldArgs a, int gx, int gy)
 {
@@ -120,9 +137,18 @@ __global__ __launch_bounds__(FX *FY) void k_h_update(FieldArgs a, int gx, int gy
         }
     }
     const float S = a.S;
-    a.Hout[0][id] = hx - S * (dyEz - dzEy);
-    a.Hout[1][id] = hy - S * (dzEx - dxEz);
-    a.Hout[2][id] = hz - S * (dxEy - dyEx);
+    const float nhx = hx - S * (dyEz - dzEy);
+    const float nhy = hy - S * (dzEx - dxEz);
+    const float nhz = hz - S * (dxEy - dyEx);
+    a.Hout[0][id] = nhx;
+    a.Hout[1][id] = nhy;
+    a.Hout[2][id] = nhz;
+    if (a.Havg[0] && in_particle_box(a, i, j, k)) {
+        // B^n of the push, (Ht^{n-1/2} + Ht^{n+1/2})/2, where particles can gather it
+        a.Havg[0][id] = 0.5f * (hx + nhx);
+        a.Havg[1][id] = 0.5f * (hy + nhy);
+        a.Havg[2][id] = 0.5f * (hz + nhz);
+    }
 }
 
 // Fused step: J_pol^{n+1/2} = J_pol^{n-1/2} + cbt E^n - d J_pol^{n-1/2} on
@@ -206,16 +232,7 @@ __global__ __launch_bounds__(FX *FY) void k_e_update(FieldArgs a, int gx, int gy
         nez -= jz;
     }
     if (a.pbox) {
-        const int n3[3] = {a.nx, a.ny, a.nz};
-        const int id3[3] = {i, j, k};
-        bool in = true;
-        for (int d = 0; d < 3; ++d) {
-            // deposits wrap on a periodic axis: clear the whole axis there
-            const int lo = a.per[d] ? 0 : a.pbox[d] - a.margin;
-            const int hi = a.per[d] ? n3[d] - 1 : a.pbox[3 + d] + a.margin;
-            in = in && id3[d] >= lo && id3[d] <= hi;
-        }
-        if (in) {
+        if (in_particle_box(a, i, j, k)) {
             nex -= a.Jb[0][id];
             ney -= a.Jb[1][id];
             nez -= a.Jb[2][id];

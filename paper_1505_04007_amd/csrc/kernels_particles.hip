@@ -2,14 +2,23 @@
 // Boris push, move, and charge-conserving (Esirkepov, first-order shape)
 // current deposition; counting sort of the particles by cell.
 //
+// Gather.  E^n and B^n = mu0 (H^{n-1/2} + H^{n+1/2})/2 are interpolated on
+// each component's own staggered lattice.  The H update also writes the
+// average of its two time levels inside the particle box, so B costs one
+// array per component.  Along x the two corners of a trilinear stencil are
+// adjacent in memory and are fetched with one 8-byte load (4 per component
+// instead of 8); a periodic x axis, where the pair can wrap, uses 4-byte loads.
+//
 // Deposit.  A move x0 -> x1 shorter than one cell touches at most three
 // nodes per axis, [b, b+2] with b = min(floor x0, floor x1).  Its current is
 // 18 Jx + 18 Jy + 18 Jz edge values on that window.  Particles are kept
 // sorted by cell, so the lanes of a wavefront mostly share a window: lanes
 // with equal windows are summed across the wavefront by recursive halving
-// (64 slots -> one slot per lane after 6 exchange rounds of shrinking width),
-// and each lane then issues at most one global float atomic.  Windows that
-// are still unresolved after a few rounds fall back to per-lane atomics.
+// (64 slots -> one slot per lane).  The two widest exchange rounds use the
+// gfx950 half-wave swaps (v_permlane32_swap, v_permlane16_swap), the four
+// narrow ones DPP lane moves, so no round goes through LDS.  Each lane then
+// issues at most one global float atomic.  Windows still unresolved after a
+// few rounds fall back to per-lane atomics.
 #include "pic_internal.hpp"
 
 namespace pic {
@@ -33,9 +42,9 @@ __device__ __forceinline__ float fold(float v, int n)
 }
 
 // Per-axis corner data of the trilinear gather on the two lattices an axis
-// can carry: nodes (integer coordinates) and half nodes.  o0/o1 are the
-// linear offsets of the two corners (clamped into the box), m0/m1 their
-// weights with the wall mask folded in (0 for a corner beyond a wall).
+// can carry: nodes (h = 0) and half nodes (h = 1).  o0/o1 are the linear
+// offsets of the two corners (clamped into the box), m0/m1 their weights
+// with the wall mask folded in (0 for a corner beyond a wall).
 struct Axis2 {
     int o0[2], o1[2];
     float m0[2], m1[2];
@@ -54,13 +63,10 @@ __device__ __forceinline__ void axis_corners(float x, int n, int per, int stride
         if (per) {
             i0 = i0 < 0 ? i0 + n : (i0 >= n ? i0 - n : i0);
             i1 = i1 < 0 ? i1 + n : (i1 >= n ? i1 - n : i1);
-            i0 = min(max(i0, 0), n - 1);
-            i1 = min(max(i1, 0), n - 1);
             ok0 = ok1 = true;
-        } else {
-            i0 = min(max(i0, 0), n - 1);
-            i1 = min(max(i1, 0), n - 1);
         }
+        i0 = min(max(i0, 0), n - 1);
+        i1 = min(max(i1, 0), n - 1);
         A.o0[h] = i0 * stride;
         A.o1[h] = i1 * stride;
         A.m0[h] = ok0 ? w0 : 0.f;
@@ -68,12 +74,60 @@ __device__ __forceinline__ void axis_corners(float x, int n, int per, int stride
     }
 }
 
+// x corners as one adjacent pair (st, st+1), st in [0, nx-2] (nx >= 2 on a
+// wall axis), with the weights of the two loaded values; a corner beyond a
+// wall gets weight 0.
+struct XPair {
+    int o[2];
+    float wa[2], wb[2];
+};
+
+__device__ __forceinline__ void x_pairs(float x, int nx, XPair &P)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const float s = h ? x - 0.5f : x;
+        const float f = floorf(s);
+        const int i = (int)f;
+        const float w1 = s - f, w0 = 1.f - w1;
+        const int st = min(max(i, 0), nx - 2);
+        // i == st: both corners in the pair; i < st (i = -1): corner 0 = st
+        // carries w1; i > st (i = nx-1): corner nx-1 = st+1 carries w0
+        P.o[h] = st;
+        P.wa[h] = i == st ? w0 : (i < st ? w1 : 0.f);
+        P.wb[h] = i == st ? w1 : (i < st ? 0.f : w0);
+    }
+}
+
+__device__ __forceinline__ float2 ld2(const float *p)
+{
+    float2 v;
+    __builtin_memcpy(&v, p, 8);  // dword-aligned 8-byte global load
+    return v;
+}
+
 // Trilinear value of a component that sits at half nodes along the axes
-// flagged (hx, hy, hz); f2 (optional) is the second time level of H, added
-// corner by corner.
+// flagged (HX, HY, HZ).
 template <int HX, int HY, int HZ>
-__device__ __forceinline__ float gather(const float *__restrict__ f, const float *__restrict__ f2,
-                                        const Axis2 &X, const Axis2 &Y, const Axis2 &Z)
+__device__ __forceinline__ float gather_pair(const float *__restrict__ f, const XPair &X,
+                                             const Axis2 &Y, const Axis2 &Z)
+{
+    float v = 0.f;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int o = X.o[HX] + (b ? Y.o1[HY] : Y.o0[HY]) + (c ? Z.o1[HZ] : Z.o0[HZ]);
+            const float w = (b ? Y.m1[HY] : Y.m0[HY]) * (c ? Z.m1[HZ] : Z.m0[HZ]);
+            const float2 p = ld2(f + o);
+            v += w * (X.wa[HX] * p.x + X.wb[HX] * p.y);
+        }
+    return v;
+}
+
+template <int HX, int HY, int HZ>
+__device__ __forceinline__ float gather_scalar(const float *__restrict__ f, const Axis2 &X,
+                                               const Axis2 &Y, const Axis2 &Z)
 {
     float v = 0.f;
 #pragma unroll
@@ -86,9 +140,7 @@ __device__ __forceinline__ float gather(const float *__restrict__ f, const float
                               (c ? Z.o1[HZ] : Z.o0[HZ]);
                 const float w = (q ? X.m1[HX] : X.m0[HX]) * (b ? Y.m1[HY] : Y.m0[HY]) *
                                 (c ? Z.m1[HZ] : Z.m0[HZ]);
-                float s = f[o];
-                if (f2) s += f2[o];
-                v += w * s;
+                v += w * f[o];
             }
     return v;
 }
@@ -163,13 +215,14 @@ __device__ __forceinline__ void make_dep(const float S0[3][3], const float dS[3]
         }
 }
 
-__device__ __forceinline__ float slot_value(const Dep &d, int s)
+// Current of slot s scaled by f (f = 0 silences a lane).
+__device__ __forceinline__ float slot_value(const Dep &d, int s, float f)
 {
     int comp, oi, oj, ok;
     slot_geom(s, comp, oi, oj, ok);
-    if (comp == 0) return d.pre[0][oi] * d.Tyz[oj][ok];
-    if (comp == 1) return d.pre[1][oj] * d.Txz[oi][ok];
-    return d.pre[2][ok] * d.Txy[oi][oj];
+    if (comp == 0) return f * d.pre[0][oi] * d.Tyz[oj][ok];
+    if (comp == 1) return f * d.pre[1][oj] * d.Txz[oi][ok];
+    return f * d.pre[2][ok] * d.Txy[oi][oj];
 }
 
 __device__ __forceinline__ float *slot_addr(const PartArgs &a, int s, int bx, int by, int bz)
@@ -188,55 +241,113 @@ __device__ __forceinline__ float *slot_addr(const PartArgs &a, int s, int bx, in
     return J + (i + a.nx * (j + a.ny * k));
 }
 
+// Lane l receives x from lane l ^ OFF (OFF = 8, 4, 2, 1), by DPP row moves.
 template <int OFF>
-__device__ __forceinline__ void halve(float *v, int lane)
+__device__ __forceinline__ float xor_lane(float x)
+{
+    const int v = __float_as_int(x);
+    int r;
+    if (OFF == 8) {
+        r = __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);  // row_ror:8
+    } else if (OFF == 4) {
+        // lanes with bit 2 clear (banks 0, 2) read l + 4, the others l - 4
+        const int t = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xf, 0x5, false);  // row_shl:4
+        r = __builtin_amdgcn_update_dpp(t, v, 0x114, 0xf, 0xa, false);            // row_shr:4
+    } else if (OFF == 2) {
+        r = __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+    } else {
+        r = __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+    }
+    return __int_as_float(r);
+}
+
+template <int OFF>
+__device__ __forceinline__ void halve_dpp(float *v, int lane)
 {
     const bool up = (lane & OFF) != 0;
 #pragma unroll
     for (int e = 0; e < OFF; ++e) {
         const float send = up ? v[e] : v[e + OFF];
         const float keep = up ? v[e + OFF] : v[e];
-        v[e] = keep + __shfl_xor(send, OFF, 64);
+        v[e] = keep + xor_lane<OFF>(send);
+    }
+}
+
+// Rounds of width 32 and 16: the lower half-wave keeps slot e, the upper
+// keeps slot e + OFF; a half-wave swap of the two registers puts each half's
+// partner values next to its own, and the sum finishes the round.
+__device__ __forceinline__ void halve32(float *v)
+{
+#pragma unroll
+    for (int e = 0; e < 32; ++e) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[e]), __float_as_uint(v[e + 32]),
+                                                        false, false);
+        v[e] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+}
+
+__device__ __forceinline__ void halve16(float *v)
+{
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[e]), __float_as_uint(v[e + 16]),
+                                                        false, false);
+        v[e] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 }
 
 // After the six rounds lane l holds the wavefront sum of slot l.
 __device__ __forceinline__ float wave_reduce64(float *v, int lane)
 {
-    halve<32>(v, lane);
-    halve<16>(v, lane);
-    halve<8>(v, lane);
-    halve<4>(v, lane);
-    halve<2>(v, lane);
-    halve<1>(v, lane);
+    halve32(v);
+    halve16(v);
+    halve_dpp<8>(v, lane);
+    halve_dpp<4>(v, lane);
+    halve_dpp<2>(v, lane);
+    halve_dpp<1>(v, lane);
     return v[0];
 }
 
 constexpr int MAX_ROUNDS = 4;
 
-template <int MODE>
+template <int MODE, int PX>
 __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
 {
     const int p = blockIdx.x * PBLOCK + threadIdx.x;
     const int lane = threadIdx.x & 63;
     bool dep = false;
-    Dep d;
+    // zeroed: a lane that does not deposit is silenced by a factor 0 in the
+    // wavefront sum, and 0 x (uninitialised register) could be NaN
+    Dep d = {};
     int base[3] = {0, 0, 0};
     if (p < a.n) {
         const float x = a.x[p], y = a.y[p], z = a.z[p];
         if (live_pos(x, y, z, a.nx, a.ny, a.nz)) {
             float u0 = a.ux[p], u1 = a.uy[p], u2 = a.uz[p];
-            Axis2 AX, AY, AZ;
-            axis_corners(x, a.nx, a.per[0], 1, AX);
+            Axis2 AY, AZ;
             axis_corners(y, a.ny, a.per[1], a.nx, AY);
             axis_corners(z, a.nz, a.per[2], a.nx * a.ny, AZ);
             // E^n and Ht^n = (Ht^{n-1/2} + Ht^{n+1/2})/2 at x^n
-            const float e0 = gather<1, 0, 0>(a.E[0], nullptr, AX, AY, AZ);
-            const float e1 = gather<0, 1, 0>(a.E[1], nullptr, AX, AY, AZ);
-            const float e2 = gather<0, 0, 1>(a.E[2], nullptr, AX, AY, AZ);
-            const float h0 = 0.5f * gather<0, 1, 1>(a.Hold[0], a.Hnew[0], AX, AY, AZ);
-            const float h1 = 0.5f * gather<1, 0, 1>(a.Hold[1], a.Hnew[1], AX, AY, AZ);
-            const float h2 = 0.5f * gather<1, 1, 0>(a.Hold[2], a.Hnew[2], AX, AY, AZ);
+            float e0, e1, e2, h0, h1, h2;
+            if (PX) {
+                Axis2 AX;
+                axis_corners(x, a.nx, 1, 1, AX);
+                e0 = gather_scalar<1, 0, 0>(a.E[0], AX, AY, AZ);
+                e1 = gather_scalar<0, 1, 0>(a.E[1], AX, AY, AZ);
+                e2 = gather_scalar<0, 0, 1>(a.E[2], AX, AY, AZ);
+                h0 = gather_scalar<0, 1, 1>(a.B[0], AX, AY, AZ);
+                h1 = gather_scalar<1, 0, 1>(a.B[1], AX, AY, AZ);
+                h2 = gather_scalar<1, 1, 0>(a.B[2], AX, AY, AZ);
+            } else {
+                XPair XP;
+                x_pairs(x, a.nx, XP);
+                e0 = gather_pair<1, 0, 0>(a.E[0], XP, AY, AZ);
+                e1 = gather_pair<0, 1, 0>(a.E[1], XP, AY, AZ);
+                e2 = gather_pair<0, 0, 1>(a.E[2], XP, AY, AZ);
+                h0 = gather_pair<0, 1, 1>(a.B[0], XP, AY, AZ);
+                h1 = gather_pair<1, 0, 1>(a.B[1], XP, AY, AZ);
+                h2 = gather_pair<1, 1, 0>(a.B[2], XP, AY, AZ);
+            }
             // relativistic Boris: half kick, rotation, half kick (u in units of c)
             const float ah = a.ah;
             const float m0 = u0 + ah * e0, m1 = u1 + ah * e1, m2 = u2 + ah * e2;
@@ -290,7 +401,7 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
         if (dep) {
 #pragma unroll
             for (int s = 0; s < 54; ++s) {
-                const float v = qd * slot_value(d, s);
+                const float v = slot_value(d, s, qd);
                 if (v != 0.f) {
                     float *ad = slot_addr(a, s, base[0], base[1], base[2]);
                     if (ad) atomicAdd(ad, v);
@@ -307,9 +418,10 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
         const int k0 = __builtin_amdgcn_readlane(key, leader);
         const bool mine = ((rem >> lane) & 1ull) && key == k0;
         const unsigned long long m = __ballot(mine);
+        const float f = mine ? 1.f : 0.f;
         float v[64];
 #pragma unroll
-        for (int s = 0; s < 54; ++s) v[s] = mine ? slot_value(d, s) : 0.f;
+        for (int s = 0; s < 54; ++s) v[s] = slot_value(d, s, f);
 #pragma unroll
         for (int s = 54; s < 64; ++s) v[s] = 0.f;
         const float tot = wave_reduce64(v, lane);
@@ -326,7 +438,7 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
     if ((rem >> lane) & 1ull) {
 #pragma unroll
         for (int s = 0; s < 54; ++s) {
-            const float v = qd * slot_value(d, s);
+            const float v = slot_value(d, s, qd);
             if (v != 0.f) {
                 float *ad = slot_addr(a, s, base[0], base[1], base[2]);
                 if (ad) atomicAdd(ad, v);
@@ -339,8 +451,13 @@ void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s)
 {
     if (a.n <= 0) return;
     const int nb = (a.n + PBLOCK - 1) / PBLOCK;
-    if (mode == 1) hipLaunchKernelGGL(k_push_deposit<1>, dim3(nb), dim3(PBLOCK), 0, s, a);
-    else hipLaunchKernelGGL(k_push_deposit<0>, dim3(nb), dim3(PBLOCK), 0, s, a);
+    if (a.per[0]) {
+        if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 1>), dim3(nb), dim3(PBLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_push_deposit<0, 1>), dim3(nb), dim3(PBLOCK), 0, s, a);
+    } else {
+        if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 0>), dim3(nb), dim3(PBLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_push_deposit<0, 0>), dim3(nb), dim3(PBLOCK), 0, s, a);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -52,6 +52,7 @@ struct pic_ctx {
     float2 *coef = nullptr;
 
     float *Jb[3] = {nullptr, nullptr, nullptr};
+    float *Havg[3] = {nullptr, nullptr, nullptr};  // B^n for the gather (particle box only)
 
     int np = 0;
     float *P[2][6] = {};
@@ -183,6 +184,7 @@ pic::FieldArgs field_args(pic_ctx *c, bool for_h)
         }
         a.Jp[d] = c->Jp[d];
         a.Jb[d] = c->Jb[d];
+        a.Havg[d] = for_h ? c->Havg[d] : nullptr;
     }
     a.coef = c->coef;
     if (!c->has_metal) {
@@ -570,6 +572,8 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         for (int d = 0; d < 3; ++d) {
             TRY(dalloc(c, &c->Jb[d], N));
             HIP_TRY(c, hipMemsetAsync(c->Jb[d], 0, N * 4, c->stream));
+            TRY(dalloc(c, &c->Havg[d], N));
+            HIP_TRY(c, hipMemsetAsync(c->Havg[d], 0, N * 4, c->stream));
         }
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         TRY(do_sort(c));
@@ -641,8 +645,7 @@ pic_status pic_step(pic_ctx *c, int64_t nsteps)
             for (int d = 0; d < 3; ++d) {
                 pa.per[d] = c->per[d];
                 pa.E[d] = c->E[d];
-                pa.Hold[d] = c->H[c->hcur][d];
-                pa.Hnew[d] = c->H[1 - c->hcur][d];
+                pa.B[d] = c->Havg[d];
                 pa.Jb[d] = c->Jb[d];
             }
             pa.S = (float)c->S;

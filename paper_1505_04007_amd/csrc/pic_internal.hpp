@@ -14,10 +14,6 @@
 
 namespace pic {
 
-// Field kernels: a 64 x 8 thread tile over (x, y) marching DZ planes in z.
-constexpr int TX = 64;
-constexpr int TY = 8;
-constexpr int DZ = 16;
 constexpr int PBLOCK = 256;  // particle kernels
 
 // CPML data of one axis.  Coefficients are per position along the axis:
@@ -43,6 +39,7 @@ struct FieldArgs {
     float *E[3];
     const float *Hin[3];
     float *Hout[3];
+    float *Havg[3];  // H kernel: (Hin + Hout)/2 written inside the particle box, or null
     PmlAxis pml[3];
     // Drude polarization current on the metal bounding box [lo, hi)
     int mlo[3], mhi[3];
@@ -61,8 +58,7 @@ struct PartArgs {
     int nx, ny, nz;
     int per[3];
     const float *E[3];
-    const float *Hold[3];
-    const float *Hnew[3];
+    const float *B[3];  // (Ht^{n-1/2} + Ht^{n+1/2}) / 2, valid inside the particle box
     float *Jb[3];
     float S;   // c dt / dx
     float ah;  // q dt / (2 m c), per V/m

@@ -218,6 +218,27 @@ def test_particles_leaving_the_box_are_dropped():
     _compare_fields(g, o, (nx, ny, nz), 1e-3)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_lanes_without_a_deposit_add_nothing(mode):
+    """Regression: in the wavefront-reduced deposit a lane that does not deposit
+    (particle lost this step, or past the end of the array) is silenced by a
+    zero factor; its deposit factors must be zero too, or 0 x garbage can be
+    NaN.  A bunch leaving through a wall over 40 steps keeps every field finite."""
+    nx, ny, nz, dx = 24, 16, 20, 5e-9
+    wpm, gm = pi.film_maps(nx, ny, nz, 3, 6)
+    rng = np.random.default_rng(pi.SEED0 + 40)
+    bunch = pi.gaussian_bunch(rng, 300, (21 * dx, 8 * dx, 12 * dx), (dx, dx, dx), 100e3)
+    w = pi.Workload("exit_walls", nx, ny, nz, dx, pi.courant_dt(dx),
+                    (native.BC_PEC, native.BC_PEC, native.BC_CPML), 4, wpm, gm, bunch,
+                    np.array([[4 * dx, 8 * dx, 7.3 * dx]]), pi.spectrum_omegas(nfreq=8), 40)
+    g = _gpu_of(w, sort_every=7, deposit_mode=mode, check_every=1)
+    o = _oracle_of(w)
+    g.step(40)
+    o.step(40)
+    assert np.isnan(g.particles()[0]).sum() > 30
+    _compare_fields(g, o, (nx, ny, nz), 1e-3)
+
+
 def test_nonfinite_field_poisons_context():
     """A NaN planted in the initial field is caught by the device flag: PIC_EUNSTABLE,
     then PIC_ESTATE on every later call."""

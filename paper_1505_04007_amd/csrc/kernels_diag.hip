@@ -99,23 +99,34 @@ __global__ void k_diag_fields(DiagArgs a)
     if ((threadIdx.x & 63) == 0) atomicAdd(&a.acc[0], s);
 }
 
-__global__ void k_diag_particles(DiagArgs a)
+// Grid-stride sums over the live particles, reduced per wavefront, then per
+// workgroup in LDS, then one FP64 atomic per workgroup and quantity (a fixed
+// grid keeps the same-address atomics to a few thousand).
+__global__ __launch_bounds__(256) void k_diag_particles(DiagArgs a)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double part[4][10];
     double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (p < a.np && live_pos(a.x[p], a.y[p], a.z[p], a.nx, a.ny, a.nz)) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.np; p += gridDim.x * blockDim.x) {
+        if (!live_pos(a.x[p], a.y[p], a.z[p], a.nx, a.ny, a.nz)) continue;
         const double X[3] = {a.x[p], a.y[p], a.z[p]};
         const double U[3] = {a.ux[p], a.uy[p], a.uz[p]};
-        v[0] = 1.0;
+        v[0] += 1.0;
         for (int d = 0; d < 3; ++d) {
-            v[1 + d] = X[d];
-            v[4 + d] = X[d] * X[d];
-            v[7 + d] = U[d];
+            v[1 + d] += X[d];
+            v[4 + d] += X[d] * X[d];
+            v[7 + d] += U[d];
         }
     }
+    const int w = threadIdx.x >> 6;
     for (int q = 0; q < 10; ++q) {
         const double t = warp_sum(v[q]);
-        if ((threadIdx.x & 63) == 0 && t != 0.0) atomicAdd(&a.acc[1 + q], t);
+        if ((threadIdx.x & 63) == 0) part[w][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const double t = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                         part[3][threadIdx.x];
+        if (t != 0.0) atomicAdd(&a.acc[1 + threadIdx.x], t);
     }
 }
 
@@ -162,7 +173,7 @@ __global__ void k_diag_gauss(DiagArgs a)
 void launch_diag_reduce(const DiagArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_diag_fields, dim3(1024), dim3(256), 0, s, a);
-    if (a.np > 0) hipLaunchKernelGGL(k_diag_particles, dim3((a.np + 255) / 256), dim3(256), 0, s, a);
+    if (a.np > 0) hipLaunchKernelGGL(k_diag_particles, dim3(1024), dim3(256), 0, s, a);
     if (a.rho) hipLaunchKernelGGL(k_diag_gauss, dim3(1024), dim3(256), 0, s, a);
 }
 

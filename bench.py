@@ -127,6 +127,70 @@ def cpu_baseline(w, nsub=100_000, steps=2):
             "particle_pushes_per_s": 1.0 / push_s}
 
 
+def step_bytes(w):
+    """Algorithmic bytes of one whole step (H + E+Drude + pushes), bunch box excluded."""
+    npart = w.bunch.n if w.bunch is not None else 0
+    return (algorithmic_bytes(w, "h_update", 0, (0, 0, 0, -1, -1, -1)) +
+            algorithmic_bytes(w, "e_update", 0, (0, 0, 0, -1, -1, -1)) + 48 * npart)
+
+
+def bench_batched(args):
+    """16 film/energy instances of uneven size: 16 sequential plain runs vs one
+    batch (one launch per kernel family per step, captured sort-period graph)."""
+    import torch
+    import pic_inputs as pi
+    from paper_1505_04007_amd import native
+
+    ws = pi.batched_sweep()
+    cells = sum(w.cells for w in ws)
+    pushes_total = 0
+    plain_s = 0.0
+    for w in ws:
+        sim = native.from_workload(w)
+        sim.step(args.warmup)
+        torch.cuda.synchronize()
+        p0 = sim.stats()["pushes"]
+        t0 = time.perf_counter()
+        sim.step(args.steps)
+        torch.cuda.synchronize()
+        plain_s += time.perf_counter() - t0
+        pushes_total += sim.stats()["pushes"] - p0
+        sim.close()
+        del sim
+    print(f"[bench] 16 plain runs: {plain_s:.3f} s", file=sys.stderr, flush=True)
+    sims = [native.from_workload(w) for w in ws]
+    batch = native.Batch(sims, use_graph=True)
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    p0 = sum(s.stats()["pushes"] for s in sims)
+    t0 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    pushes = sum(s.stats()["pushes"] for s in sims) - p0
+    print(f"[bench] batched: {secs:.3f} s", file=sys.stderr, flush=True)
+    gcells = cells * args.steps / secs / 1e9
+    plain_g = cells * args.steps / plain_s / 1e9
+    sb = sum(step_bytes(w) for w in ws)
+    ach = sb * args.steps / secs / 1e9
+    out = {"metric": METRIC, "value": round(gcells, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * secs / args.steps, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched16_film5-80nm_128x64x64-192x96x96", "instances": len(ws),
+                      "cells": cells, "particles": sum(w.bunch.n for w in ws), "sort_every": 20,
+                      "parallelism": "single-gpu"},
+           "particle_pushes_per_s": round(pushes / secs, 1),
+           "plain_sequential": {"value": round(plain_g, 3), "unit": "Gcell-updates/s",
+                                "particle_pushes_per_s": round(pushes_total / plain_s, 1)},
+           "batched_vs_plain": round(gcells / plain_g, 3),
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "whole batched step (H + push + E+Drude, algorithmic bytes)"},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +223,10 @@ def main():
     import torch
     from paper_1505_04007_amd import native
 
+    if args.workload == "batched16":
+        torch.cuda.set_device(0)
+        bench_batched(args)
+        return
     w = workload(args.workload)
     torch.cuda.set_device(0)
     sim = native.from_workload(w, timing=True, deposit_mode=args.deposit_mode)

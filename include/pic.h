@@ -201,6 +201,31 @@ pic_status pic_timing(pic_ctx *ctx, double *ms_total, int64_t *launches, int res
 /* Destroy a context and free everything it owns.  NULL is a no-op. */
 void pic_destroy(pic_ctx *ctx);
 
+/*
+ * Batched simulations (e.g. a sweep over film thickness and bunch energy):
+ * advance n independent contexts together with one launch per kernel family
+ * per step for all of them, instead of one per context.
+ *
+ * pic_batch_create: ctxs[0..n) are existing contexts (1 <= n <= 64) created
+ *   on one stream; those with particles must share sort_every and
+ *   deposit_mode.  The batch borrows them: they must outlive it and stay
+ *   valid; reading them (pic_probe, pic_read_*, pic_diag, ...) between batch
+ *   steps is allowed.  use_graph = 1 captures one sort period (sort_every
+ *   steps and the sorts that follow, or 10 steps without particles) as a HIP
+ *   graph at creation and replays it whenever all members are at the start
+ *   of a sort period; other steps are issued directly.
+ * pic_batch_step: advance every member by nsteps steps.  Each member's
+ *   results equal those of pic_step on that member alone (same kernels, same
+ *   per-cell arithmetic).  No non-finite poll is made; use pic_diag.
+ * Errors: PIC_EINVAL (arguments), PIC_ESTATE (a poisoned member),
+ *   PIC_EDEVICE, PIC_ENOMEM; the message is in pic_batch_last_error.
+ */
+typedef struct pic_batch pic_batch;
+pic_status pic_batch_create(pic_batch **batch, pic_ctx *const *ctxs, int32_t n, int32_t use_graph);
+pic_status pic_batch_step(pic_batch *batch, int64_t nsteps);
+void pic_batch_destroy(pic_batch *batch);
+const char *pic_batch_last_error(const pic_batch *batch);
+
 /* Message of the last error on ctx (or of the last failed pic_init when ctx
  * is NULL).  Owned by the library; valid until the next call on ctx. */
 const char *pic_last_error(const pic_ctx *ctx);

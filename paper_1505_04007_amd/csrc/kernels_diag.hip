@@ -6,10 +6,13 @@ namespace pic {
 // F_p(w_m) += dt Ez_p^n exp(-i w_m n dt) for the E^n just computed (Sec. IV,
 // Figs. 6-7: Ez at the film surface and its spectrum).  The phase is
 // evaluated directly in FP64 each step.
-__global__ void k_probe(ProbeArgs a)
+// The last kernel of a step: after sampling, it advances the step clock
+// (H parity, steps since the sort, step number) for the next step.
+__device__ __forceinline__ void probe_body(const ProbeArgs &a)
 {
     const int t = threadIdx.x;
-    const double tn = (double)a.step * a.dt;
+    const long long n1 = a.st->step + 1;  // E^{n+1} was just computed
+    const double tn = (double)n1 * a.dt;
     for (int q = t; q < a.nprobe * a.nfreq; q += blockDim.x) {
         const int p = q / a.nfreq, f = q - p * a.nfreq;
         const double ez = (double)a.Ez[a.pidx[p]];
@@ -18,14 +21,29 @@ __global__ void k_probe(ProbeArgs a)
         a.fre[q] += a.dt * ez * cs;
         a.fim[q] -= a.dt * ez * sn;
     }
-    if (a.series && t < a.nprobe && a.step - 1 < a.series_len)
-        a.series[(a.step - 1) * a.nprobe + t] = a.Ez[a.pidx[t]];
+    if (a.series && t < a.nprobe && n1 - 1 < a.series_len)
+        a.series[(n1 - 1) * a.nprobe + t] = a.Ez[a.pidx[t]];
+    __syncthreads();  // every thread has read the clock before it moves
+    if (t == 0) {
+        DevState *st = a.st;
+        st->parity ^= 1;
+        st->since_sort += 1;
+        st->step = n1;
+    }
 }
+
+__global__ void k_probe(ProbeArgs a) { probe_body(a); }
+
+__global__ void k_probe_batch(const ProbeArgs *args) { probe_body(args[blockIdx.x]); }
 
 void launch_probe(const ProbeArgs &a, hipStream_t s)
 {
-    if (a.nprobe <= 0) return;
     hipLaunchKernelGGL(k_probe, dim3(1), dim3(256), 0, s, a);
+}
+
+void launch_probe_batch(const ProbeArgs *args, int n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_probe_batch, dim3(n), dim3(256), 0, s, args);
 }
 
 // Node-centred cloud-in-cell charge density in FP64 (nodes (nx+1)(ny+1)(nz+1)).

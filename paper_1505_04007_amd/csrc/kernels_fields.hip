@@ -14,13 +14,12 @@
 //
 // Workgroups are remapped so that the tiles one XCD executes form a
 // contiguous range in (x, y, z): neighbours in y and z then share that XCD's
-// L2.
+// L2.  The batched entry points run the same per-cell code for many
+// simulations in one launch: the remapped tile index is looked up in a
+// prefix table of tiles per simulation.
 #include "pic_internal.hpp"
 
 namespace pic {
-
-constexpr int FX = 64;
-constexpr int FY = 4;
 
 __device__ __forceinline__ int lin(const FieldArgs &a, int i, int j, int k)
 {
@@ -42,14 +41,11 @@ __device__ __forceinline__ int nb_off(int i, int d, int n, int per, int st, bool
 // Workgroup -> tile with XCD locality: the 8 XCDs receive workgroups round
 // robin, so workgroup b runs on XCD b % 8; give each XCD a contiguous block
 // of tiles.
-__device__ __forceinline__ void tile_of(int gx, int gy, int &bx, int &by, int &bz)
+__device__ __forceinline__ int xcd_tile()
 {
     const int B = gridDim.x;
     const int b = blockIdx.x;
-    const int t = (B % 8 == 0) ? (b % 8) * (B / 8) + b / 8 : b;
-    bx = t % gx;
-    by = (t / gx) % gy;
-    bz = t / (gx * gy);
+    return (B % 8 == 0) ? (b % 8) * (B / 8) + b / 8 : b;
 }
 
 __device__ __forceinline__ float cpml(float *__restrict__ psi, int sid, float b, float c, float ik,
@@ -65,27 +61,23 @@ __device__ __forceinline__ int slab_p(int q, int n, int np) { return q < np ? q 
 // Inside the live-particle cell box of the last sort widened by the margin
 // (every cell a particle can gather from or deposit to this step); a
 // periodic axis counts whole because deposits and gathers wrap there.
-__device__ __forceinline__ bool in_particle_box(const FieldArgs &a, int i, int j, int k)
+__device__ __forceinline__ bool in_particle_box(const FieldArgs &a, int margin, int i, int j, int k)
 {
     const int n3[3] = {a.nx, a.ny, a.nz};
     const int id3[3] = {i, j, k};
     bool in = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int lo = a.per[d] ? 0 : a.pbox[d] - a.margin;
-        const int hi = a.per[d] ? n3[d] - 1 : a.pbox[3 + d] + a.margin;
+        const int lo = a.per[d] ? 0 : a.pbox[d] - margin;
+        const int hi = a.per[d] ? n3[d] - 1 : a.pbox[3 + d] + margin;
         in = in && id3[d] >= lo && id3[d] <= hi;
     }
     return in;
 }
 
 // H^{n+1/2} = H^{n-1/2} - S curl E^n  (vacuum form for every cell).
-__global__ __launch_bounds__(FX *FY) void k_h_update(FieldArgs a, int gx, int gy)
+__device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, int i, int j, int k)
 {
-    int bx, by, k;
-    tile_of(gx, gy, bx, by, k);
-    const int i = bx * FX + threadIdx.x, j = by * FY + threadIdx.y;
-    if (i >= a.nx || j >= a.ny) return;
     const int id = lin(a, i, j, k);
     const int sx = 1, sy = a.nx, sz = a.nx * a.ny;
     bool okx, oky, okz;
@@ -95,11 +87,17 @@ __global__ __launch_bounds__(FX *FY) void k_h_update(FieldArgs a, int gx, int gy
     const float *__restrict__ Ex = a.E[0];
     const float *__restrict__ Ey = a.E[1];
     const float *__restrict__ Ez = a.E[2];
+    const float *__restrict__ H0 = par ? a.H[1][0] : a.H[0][0];
+    const float *__restrict__ H1 = par ? a.H[1][1] : a.H[0][1];
+    const float *__restrict__ H2 = par ? a.H[1][2] : a.H[0][2];
+    float *__restrict__ O0 = par ? a.H[0][0] : a.H[1][0];
+    float *__restrict__ O1 = par ? a.H[0][1] : a.H[1][1];
+    float *__restrict__ O2 = par ? a.H[0][2] : a.H[1][2];
     const float ex = Ex[id], ey = Ey[id], ez = Ez[id];
     float eyx = Ey[id + ox], ezx = Ez[id + ox];
     float exy = Ex[id + oy], ezy = Ez[id + oy];
     float exz = Ex[id + oz], eyz = Ey[id + oz];
-    const float hx = a.Hin[0][id], hy = a.Hin[1][id], hz = a.Hin[2][id];
+    const float hx = H0[id], hy = H1[id], hz = H2[id];
     eyx = okx ? eyx : 0.f;
     ezx = okx ? ezx : 0.f;
     exy = oky ? exy : 0.f;
@@ -140,10 +138,10 @@ __global__ __launch_bounds__(FX *FY) void k_h_update(FieldArgs a, int gx, int gy
     const float nhx = hx - S * (dyEz - dzEy);
     const float nhy = hy - S * (dzEx - dxEz);
     const float nhz = hz - S * (dxEy - dyEx);
-    a.Hout[0][id] = nhx;
-    a.Hout[1][id] = nhy;
-    a.Hout[2][id] = nhz;
-    if (a.Havg[0] && in_particle_box(a, i, j, k)) {
+    O0[id] = nhx;
+    O1[id] = nhy;
+    O2[id] = nhz;
+    if (a.Havg[0] && in_particle_box(a, margin, i, j, k)) {
         // B^n of the push, (Ht^{n-1/2} + Ht^{n+1/2})/2, where particles can gather it
         a.Havg[0][id] = 0.5f * (hx + nhx);
         a.Havg[1][id] = 0.5f * (hy + nhy);
@@ -155,21 +153,18 @@ __global__ __launch_bounds__(FX *FY) void k_h_update(FieldArgs a, int gx, int gy
 // metal edges, then E^{n+1} = E^n + S curl H^{n+1/2} - J_pol^{n+1/2} -
 // J_b^{n+1/2}; J_b is cleared after use.  Tangential E on PEC walls is
 // never written.
-__global__ __launch_bounds__(FX *FY) void k_e_update(FieldArgs a, int gx, int gy)
+__device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, int i, int j, int k)
 {
-    int bx, by, k;
-    tile_of(gx, gy, bx, by, k);
-    const int i = bx * FX + threadIdx.x, j = by * FY + threadIdx.y;
-    if (i >= a.nx || j >= a.ny) return;
     const int id = lin(a, i, j, k);
     const int sx = 1, sy = a.nx, sz = a.nx * a.ny;
     bool okx, oky, okz;
     const int ox = nb_off(i, -1, a.nx, a.per[0], sx, okx);
     const int oy = nb_off(j, -1, a.ny, a.per[1], sy, oky);
     const int oz = nb_off(k, -1, a.nz, a.per[2], sz, okz);
-    const float *__restrict__ Hx = a.Hin[0];
-    const float *__restrict__ Hy = a.Hin[1];
-    const float *__restrict__ Hz = a.Hin[2];
+    // H^{n+1/2}: written by this step's H update into H[par ^ 1]
+    const float *__restrict__ Hx = par ? a.H[0][0] : a.H[1][0];
+    const float *__restrict__ Hy = par ? a.H[0][1] : a.H[1][1];
+    const float *__restrict__ Hz = par ? a.H[0][2] : a.H[1][2];
     const float hx = Hx[id], hy = Hy[id], hz = Hz[id];
     float hyx = Hy[id + ox], hzx = Hz[id + ox];
     float hxy = Hx[id + oy], hzy = Hz[id + oy];
@@ -231,15 +226,13 @@ __global__ __launch_bounds__(FX *FY) void k_e_update(FieldArgs a, int gx, int gy
         ney -= jy;
         nez -= jz;
     }
-    if (a.pbox) {
-        if (in_particle_box(a, i, j, k)) {
-            nex -= a.Jb[0][id];
-            ney -= a.Jb[1][id];
-            nez -= a.Jb[2][id];
-            a.Jb[0][id] = 0.f;
-            a.Jb[1][id] = 0.f;
-            a.Jb[2][id] = 0.f;
-        }
+    if (a.pbox && in_particle_box(a, margin, i, j, k)) {
+        nex -= a.Jb[0][id];
+        ney -= a.Jb[1][id];
+        nez -= a.Jb[2][id];
+        a.Jb[0][id] = 0.f;
+        a.Jb[1][id] = 0.f;
+        a.Jb[2][id] = 0.f;
     }
     const bool wx = !a.per[0] && i == 0, wy = !a.per[1] && j == 0, wz = !a.per[2] && k == 0;
     if (!(wy || wz)) a.E[0][id] = nex;
@@ -248,16 +241,81 @@ __global__ __launch_bounds__(FX *FY) void k_e_update(FieldArgs a, int gx, int gy
     if (!(isfinite(nex) && isfinite(ney) && isfinite(nez))) atomicOr(a.nan_flag, 1);
 }
 
+// Decompose a tile index of one simulation into (i, j, k); false when the
+// thread lies past the grid's x / y extent.
+__device__ __forceinline__ bool tile_cell(const FieldArgs &a, int t, int &i, int &j, int &k)
+{
+    const int bx = t % a.gx, by = (t / a.gx) % a.gy;
+    k = t / (a.gx * a.gy);
+    i = bx * FX + threadIdx.x;
+    j = by * FY + threadIdx.y;
+    return i < a.nx && j < a.ny;
+}
+
+__global__ __launch_bounds__(FX *FY) void k_h_update(FieldArgs a)
+{
+    int i, j, k;
+    if (!tile_cell(a, xcd_tile(), i, j, k)) return;
+    const DevState s = *a.st;
+    h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
+}
+
+__global__ __launch_bounds__(FX *FY) void k_e_update(FieldArgs a)
+{
+    int i, j, k;
+    if (!tile_cell(a, xcd_tile(), i, j, k)) return;
+    const DevState s = *a.st;
+    e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
+}
+
+// Simulation owning global work unit t: start[q] <= t < start[q + 1].
+__device__ __forceinline__ int owner(const int *start, int n, int t)
+{
+    int q = 0;
+    while (q + 1 < n && start[q + 1] <= t) ++q;
+    return q;
+}
+
+__global__ __launch_bounds__(FX *FY) void k_h_update_batch(const FieldArgs *args, const int *start, int n)
+{
+    const int t = xcd_tile();
+    const int q = owner(start, n, t);
+    const FieldArgs &a = args[q];
+    int i, j, k;
+    if (!tile_cell(a, t - start[q], i, j, k)) return;
+    const DevState s = *a.st;
+    h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
+}
+
+__global__ __launch_bounds__(FX *FY) void k_e_update_batch(const FieldArgs *args, const int *start, int n)
+{
+    const int t = xcd_tile();
+    const int q = owner(start, n, t);
+    const FieldArgs &a = args[q];
+    int i, j, k;
+    if (!tile_cell(a, t - start[q], i, j, k)) return;
+    const DevState s = *a.st;
+    e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
+}
+
 void launch_h_update(const FieldArgs &a, hipStream_t s)
 {
-    const int gx = (a.nx + FX - 1) / FX, gy = (a.ny + FY - 1) / FY;
-    hipLaunchKernelGGL(k_h_update, dim3(gx * gy * a.nz), dim3(FX, FY), 0, s, a, gx, gy);
+    hipLaunchKernelGGL(k_h_update, dim3(field_tiles(a.nx, a.ny, a.nz)), dim3(FX, FY), 0, s, a);
 }
 
 void launch_e_update(const FieldArgs &a, hipStream_t s)
 {
-    const int gx = (a.nx + FX - 1) / FX, gy = (a.ny + FY - 1) / FY;
-    hipLaunchKernelGGL(k_e_update, dim3(gx * gy * a.nz), dim3(FX, FY), 0, s, a, gx, gy);
+    hipLaunchKernelGGL(k_e_update, dim3(field_tiles(a.nx, a.ny, a.nz)), dim3(FX, FY), 0, s, a);
+}
+
+void launch_h_update_batch(const FieldArgs *args, const int *start, int n, int total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_h_update_batch, dim3(total), dim3(FX, FY), 0, s, args, start, n);
+}
+
+void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_e_update_batch, dim3(total), dim3(FX, FY), 0, s, args, start, n);
 }
 
 }  // namespace pic

@@ -311,19 +311,26 @@ __device__ __forceinline__ float wave_reduce64(float *v, int lane)
 constexpr int MAX_ROUNDS = 4;
 
 template <int MODE, int PX>
-__global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
+__device__ __forceinline__ void push_body(const PartArgs &a, int blk)
 {
-    const int p = blockIdx.x * PBLOCK + threadIdx.x;
+    const int p = blk * PBLOCK + threadIdx.x;
     const int lane = threadIdx.x & 63;
+    const int pc = a.st->pcur;
+    float *__restrict__ X = a.P[pc][0];
+    float *__restrict__ Y = a.P[pc][1];
+    float *__restrict__ Z = a.P[pc][2];
+    float *__restrict__ UX = a.P[pc][3];
+    float *__restrict__ UY = a.P[pc][4];
+    float *__restrict__ UZ = a.P[pc][5];
     bool dep = false;
     // zeroed: a lane that does not deposit is silenced by a factor 0 in the
     // wavefront sum, and 0 x (uninitialised register) could be NaN
     Dep d = {};
     int base[3] = {0, 0, 0};
     if (p < a.n) {
-        const float x = a.x[p], y = a.y[p], z = a.z[p];
+        const float x = X[p], y = Y[p], z = Z[p];
         if (live_pos(x, y, z, a.nx, a.ny, a.nz)) {
-            float u0 = a.ux[p], u1 = a.uy[p], u2 = a.uz[p];
+            float u0 = UX[p], u1 = UY[p], u2 = UZ[p];
             Axis2 AY, AZ;
             axis_corners(y, a.ny, a.per[1], a.nx, AY);
             axis_corners(z, a.nz, a.per[2], a.nx * a.ny, AZ);
@@ -331,7 +338,7 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
             float e0, e1, e2, h0, h1, h2;
             if (PX) {
                 Axis2 AX;
-                axis_corners(x, a.nx, 1, 1, AX);
+                axis_corners(x, a.nx, a.per[0], 1, AX);
                 e0 = gather_scalar<1, 0, 0>(a.E[0], AX, AY, AZ);
                 e1 = gather_scalar<0, 1, 0>(a.E[1], AX, AY, AZ);
                 e2 = gather_scalar<0, 0, 1>(a.E[2], AX, AY, AZ);
@@ -368,11 +375,11 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
                              (!a.per[0] && !(x1 >= 0.f && x1 < (float)a.nx)) ||
                              (!a.per[1] && !(y1 >= 0.f && y1 < (float)a.ny)) ||
                              (!a.per[2] && !(z1 >= 0.f && z1 < (float)a.nz));
-            a.ux[p] = u0;
-            a.uy[p] = u1;
-            a.uz[p] = u2;
+            UX[p] = u0;
+            UY[p] = u1;
+            UZ[p] = u2;
             if (out) {
-                a.x[p] = -1.f;  // left the box: deactivated, last move not deposited
+                X[p] = -1.f;  // left the box: deactivated, last move not deposited
             } else {
                 // written out per axis: constant indices keep S0/dS in registers
                 float S0[3][3], dS[3][3];
@@ -387,9 +394,9 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
                 if (a.per[0]) x1 = fold(x1, a.nx);
                 if (a.per[1]) y1 = fold(y1, a.ny);
                 if (a.per[2]) z1 = fold(z1, a.nz);
-                a.x[p] = x1;
-                a.y[p] = y1;
-                a.z[p] = z1;
+                X[p] = x1;
+                Y[p] = y1;
+                Z[p] = z1;
             }
         }
     }
@@ -447,6 +454,24 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
     }
 }
 
+template <int MODE, int PX>
+__global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
+{
+    push_body<MODE, PX>(a, blockIdx.x);
+}
+
+// Many simulations in one launch: workgroup b belongs to the simulation q
+// with start[q] <= b < start[q + 1].
+template <int MODE, int PX>
+__global__ __launch_bounds__(PBLOCK) void k_push_deposit_batch(const PartArgs *args, const int *start,
+                                                               int n)
+{
+    const int b = blockIdx.x;
+    int q = 0;
+    while (q + 1 < n && start[q + 1] <= b) ++q;
+    push_body<MODE, PX>(args[q], b - start[q]);
+}
+
 void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s)
 {
     if (a.n <= 0) return;
@@ -457,6 +482,19 @@ void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s)
     } else {
         if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 0>), dim3(nb), dim3(PBLOCK), 0, s, a);
         else hipLaunchKernelGGL((k_push_deposit<0, 0>), dim3(nb), dim3(PBLOCK), 0, s, a);
+    }
+}
+
+// `mode` bit 0: per-lane atomics; bit 1: some simulation has a periodic x axis.
+void launch_push_deposit_batch(const PartArgs *args, const int *start, int n, int total, int mode,
+                               hipStream_t s)
+{
+    if (total <= 0) return;
+    switch (mode & 3) {
+    case 0: hipLaunchKernelGGL((k_push_deposit_batch<0, 0>), dim3(total), dim3(PBLOCK), 0, s, args, start, n); break;
+    case 1: hipLaunchKernelGGL((k_push_deposit_batch<1, 0>), dim3(total), dim3(PBLOCK), 0, s, args, start, n); break;
+    case 2: hipLaunchKernelGGL((k_push_deposit_batch<0, 1>), dim3(total), dim3(PBLOCK), 0, s, args, start, n); break;
+    default: hipLaunchKernelGGL((k_push_deposit_batch<1, 1>), dim3(total), dim3(PBLOCK), 0, s, args, start, n); break;
     }
 }
 
@@ -485,8 +523,9 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
     if (threadIdx.x < 6) bb[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
     __syncthreads();
     const int p = blockIdx.x * PBLOCK + threadIdx.x;
+    const int pc = a.st->pcur;
     if (p < a.n) {
-        const float x = a.src[0][p], y = a.src[1][p], z = a.src[2][p];
+        const float x = a.P[pc][0][p], y = a.P[pc][1][p], z = a.P[pc][2][p];
         int key = a.ncell;
         if (live_pos(x, y, z, a.nx, a.ny, a.nz)) {
             const int i = min((int)x, a.nx - 1);
@@ -585,16 +624,25 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_scatter(SortArgs a)
 {
     const int p = blockIdx.x * PBLOCK + threadIdx.x;
     if (p >= a.n) return;
+    const int pc = a.st->pcur;
     const int dst = a.counts[a.key[p]] + a.rank[p];
-    for (int c = 0; c < 6; ++c) a.dst[c][dst] = a.src[c][p];
-    a.id_dst[dst] = a.id_src[p];
+    for (int c = 0; c < 6; ++c) a.P[pc ^ 1][c][dst] = a.P[pc][c][p];
+    a.id[pc ^ 1][dst] = a.id[pc][p];
+}
+
+// After the scatter: the sorted set becomes current and the sort clock restarts.
+__global__ void k_sort_done(DevState *st)
+{
+    if (threadIdx.x == 0) {
+        st->pcur ^= 1;
+        st->since_sort = 0;
+    }
 }
 
 int scan_tmp_size(int n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
-void launch_sort(const SortArgs &a, int *scan_tmp, int scan_tmp_len, hipStream_t s)
+void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s)
 {
-    (void)scan_tmp_len;
     const int ncount = a.ncell + 1;
     launch_fill_i32(a.counts, 0, ncount, s);
     launch_fill_i32(a.box, INT_MAX, 3, s);
@@ -611,6 +659,7 @@ void launch_sort(const SortArgs &a, int *scan_tmp, int scan_tmp_len, hipStream_t
         const int nb = (a.n + PBLOCK - 1) / PBLOCK;
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(PBLOCK), 0, s, a);
     }
+    hipLaunchKernelGGL(k_sort_done, dim3(1), dim3(64), 0, s, a.st);
 }
 
 }  // namespace pic

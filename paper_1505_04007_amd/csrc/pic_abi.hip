@@ -43,8 +43,14 @@ struct pic_ctx {
 
     float *E[3] = {nullptr, nullptr, nullptr};
     float *H[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-    int hcur = 0;
+    int hcur = 0;  // host mirror of DevState.parity after the last step
     pic::PmlAxis pml[3];
+    pic::DevState *dstate = nullptr;  // step clock advanced by the kernels
+    // argument blocks, fixed after pic_init (the step clock lives in dstate)
+    pic::FieldArgs fa{};
+    pic::PartArgs pa{};
+    pic::SortArgs sa{};
+    pic::ProbeArgs pr{};
 
     int mlo[3] = {0, 0, 0}, mhi[3] = {0, 0, 0};
     bool has_metal = false;
@@ -160,40 +166,84 @@ void cpml_coeff(const pic_grid &g, int npml, int n, double pos, double dx, doubl
     ik = (float)(1.0 / kap);
 }
 
-pic::FieldArgs field_args(pic_ctx *c, bool for_h)
+// Fill the argument blocks once; nothing in them changes from step to step.
+void build_args(pic_ctx *c)
 {
-    pic::FieldArgs a{};
+    pic::FieldArgs &a = c->fa;
+    a = pic::FieldArgs{};
     a.nx = c->n[0];
     a.ny = c->n[1];
     a.nz = c->n[2];
+    a.gx = (c->n[0] + pic::FX - 1) / pic::FX;
+    a.gy = (c->n[1] + pic::FY - 1) / pic::FY;
+    a.S = (float)c->S;
     for (int d = 0; d < 3; ++d) {
         a.per[d] = c->per[d];
         a.pml[d] = c->pml[d];
-        a.mlo[d] = c->mlo[d];
-        a.mhi[d] = c->mhi[d];
-    }
-    a.S = (float)c->S;
-    for (int d = 0; d < 3; ++d) {
+        a.mlo[d] = c->has_metal ? c->mlo[d] : 0;
+        a.mhi[d] = c->has_metal ? c->mhi[d] : 0;
         a.E[d] = c->E[d];
-        if (for_h) {
-            a.Hin[d] = c->H[c->hcur][d];
-            a.Hout[d] = c->H[1 - c->hcur][d];
-        } else {
-            a.Hin[d] = c->H[c->hcur][d];
-            a.Hout[d] = nullptr;
-        }
+        a.H[0][d] = c->H[0][d];
+        a.H[1][d] = c->H[1][d];
+        a.Havg[d] = c->Havg[d];
         a.Jp[d] = c->Jp[d];
         a.Jb[d] = c->Jb[d];
-        a.Havg[d] = for_h ? c->Havg[d] : nullptr;
     }
     a.coef = c->coef;
-    if (!c->has_metal) {
-        for (int d = 0; d < 3; ++d) a.mlo[d] = a.mhi[d] = 0;
-    }
     a.pbox = c->np > 0 ? c->box : nullptr;
-    a.margin = 3 + (int)std::ceil((double)(c->since_sort + 1) * c->S);
     a.nan_flag = c->d_nan;
-    return a;
+    a.st = c->dstate;
+
+    pic::PartArgs &pa = c->pa;
+    pa = pic::PartArgs{};
+    pa.n = c->np;
+    for (int s2 = 0; s2 < 2; ++s2)
+        for (int q = 0; q < 6; ++q) pa.P[s2][q] = c->P[s2][q];
+    pa.nx = c->n[0];
+    pa.ny = c->n[1];
+    pa.nz = c->n[2];
+    for (int d = 0; d < 3; ++d) {
+        pa.per[d] = c->per[d];
+        pa.E[d] = c->E[d];
+        pa.B[d] = c->Havg[d];
+        pa.Jb[d] = c->Jb[d];
+    }
+    pa.S = (float)c->S;
+    pa.ah = c->ah;
+    pa.qd = c->qd;
+    pa.pushes = c->d_pushes;
+    pa.st = c->dstate;
+
+    pic::SortArgs &sa = c->sa;
+    sa = pic::SortArgs{};
+    sa.n = c->np;
+    sa.nx = c->n[0];
+    sa.ny = c->n[1];
+    sa.nz = c->n[2];
+    sa.ncell = c->n[0] * c->n[1] * c->n[2];
+    for (int s2 = 0; s2 < 2; ++s2) {
+        for (int q = 0; q < 6; ++q) sa.P[s2][q] = c->P[s2][q];
+        sa.id[s2] = c->pid[s2];
+    }
+    sa.key = c->key;
+    sa.rank = c->rank;
+    sa.counts = c->counts;
+    sa.box = c->box;
+    sa.st = c->dstate;
+
+    pic::ProbeArgs &pr = c->pr;
+    pr = pic::ProbeArgs{};
+    pr.nprobe = c->nprobe;
+    pr.nfreq = c->nfreq;
+    pr.pidx = c->pidx;
+    pr.omega = c->omega;
+    pr.fre = c->fre;
+    pr.fim = c->fim;
+    pr.series = c->series;
+    pr.series_len = c->series_len;
+    pr.dt = c->dt;
+    pr.Ez = c->E[2];
+    pr.st = c->dstate;
 }
 
 void tstart(pic_ctx *c, int fam)
@@ -215,28 +265,42 @@ void tstop(pic_ctx *c, int fam)
 pic_status do_sort(pic_ctx *c)
 {
     if (c->np <= 0) return PIC_OK;
-    pic::SortArgs s{};
-    s.n = c->np;
-    s.nx = c->n[0];
-    s.ny = c->n[1];
-    s.nz = c->n[2];
-    s.ncell = c->n[0] * c->n[1] * c->n[2];
-    for (int q = 0; q < 6; ++q) {
-        s.src[q] = c->P[c->pcur][q];
-        s.dst[q] = c->P[1 - c->pcur][q];
-    }
-    s.id_src = c->pid[c->pcur];
-    s.id_dst = c->pid[1 - c->pcur];
-    s.key = c->key;
-    s.rank = c->rank;
-    s.counts = c->counts;
-    s.box = c->box;
     tstart(c, 4);
-    pic::launch_sort(s, c->scan_tmp, c->scan_len, c->stream);
+    pic::launch_sort(c->sa, c->scan_tmp, c->stream);
     tstop(c, 4);
     HIP_TRY(c, hipGetLastError());
-    c->pcur = 1 - c->pcur;
+    c->pcur = 1 - c->pcur;  // mirrors the device-side flip in the sort's last kernel
     c->since_sort = 0;
+    return PIC_OK;
+}
+
+// One step on the context's stream (no synchronisation); host mirrors of the
+// device step clock advance with it.
+pic_status step_once(pic_ctx *c)
+{
+    if (c->np > 0 && c->sort_every > 0 && c->since_sort >= c->sort_every) TRY(do_sort(c));
+    // 1. H^{n+1/2}
+    tstart(c, 0);
+    pic::launch_h_update(c->fa, c->stream);
+    tstop(c, 0);
+    // 2. gather E^n, B^n; Boris; move; deposit J_b^{n+1/2}
+    if (c->np > 0) {
+        tstart(c, 1);
+        pic::launch_push_deposit(c->pa, c->deposit_mode, c->stream);
+        tstop(c, 1);
+    }
+    // 3-4. Drude J^{n+1/2} (Eq. 6), E^{n+1} (Eq. 8 with the bunch current)
+    tstart(c, 2);
+    pic::launch_e_update(c->fa, c->stream);
+    tstop(c, 2);
+    // 5. probes; advances the device step clock
+    tstart(c, 3);
+    pic::launch_probe(c->pr, c->stream);
+    tstop(c, 3);
+    c->hcur = 1 - c->hcur;
+    c->step++;
+    c->since_sort++;
+    HIP_TRY(c, hipGetLastError());
     return PIC_OK;
 }
 
@@ -393,6 +457,8 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
     HIP_TRY(c, hipMemsetAsync(c->d_nan, 0, 4, c->stream));
     TRY(dalloc(c, &c->acc, 16));
     TRY(dalloc(c, &c->d_live, 1));
+    TRY(dalloc(c, &c->dstate, 1));
+    HIP_TRY(c, hipMemsetAsync(c->dstate, 0, sizeof(pic::DevState), c->stream));
 
     // host staging kept alive until the final synchronisation
     std::vector<std::vector<float>> stage;
@@ -576,6 +642,7 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
             HIP_TRY(c, hipMemsetAsync(c->Havg[d], 0, N * 4, c->stream));
         }
         HIP_TRY(c, hipStreamSynchronize(c->stream));
+        build_args(c);
         TRY(do_sort(c));
         if (c->diag) {
             const size_t nodes = (size_t)(nn[0] + 1) * (nn[1] + 1) * (nn[2] + 1);
@@ -588,6 +655,7 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
             HIP_TRY(c, hipGetLastError());
         }
     }
+    build_args(c);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     HIP_TRY(c, hipGetLastError());
     c->since_sort = 0;
@@ -623,67 +691,7 @@ pic_status pic_step(pic_ctx *c, int64_t nsteps)
     CHECK_CTX(c);
     if (nsteps < 0) return fail(c, PIC_EINVAL, "nsteps must be >= 0");
     for (int64_t it = 0; it < nsteps; ++it) {
-        if (c->np > 0 && c->sort_every > 0 && c->since_sort >= c->sort_every) TRY(do_sort(c));
-        // 1. H^{n+1/2}
-        pic::FieldArgs fh = field_args(c, true);
-        tstart(c, 0);
-        pic::launch_h_update(fh, c->stream);
-        tstop(c, 0);
-        // 2. gather E^n, B^n; Boris; move; deposit J_b^{n+1/2}
-        if (c->np > 0) {
-            pic::PartArgs pa{};
-            pa.n = c->np;
-            pa.x = c->P[c->pcur][0];
-            pa.y = c->P[c->pcur][1];
-            pa.z = c->P[c->pcur][2];
-            pa.ux = c->P[c->pcur][3];
-            pa.uy = c->P[c->pcur][4];
-            pa.uz = c->P[c->pcur][5];
-            pa.nx = c->n[0];
-            pa.ny = c->n[1];
-            pa.nz = c->n[2];
-            for (int d = 0; d < 3; ++d) {
-                pa.per[d] = c->per[d];
-                pa.E[d] = c->E[d];
-                pa.B[d] = c->Havg[d];
-                pa.Jb[d] = c->Jb[d];
-            }
-            pa.S = (float)c->S;
-            pa.ah = c->ah;
-            pa.qd = c->qd;
-            pa.pushes = c->d_pushes;
-            tstart(c, 1);
-            pic::launch_push_deposit(pa, c->deposit_mode, c->stream);
-            tstop(c, 1);
-        }
-        c->hcur = 1 - c->hcur;
-        // 3-4. Drude J^{n+1/2} (Eq. 6), E^{n+1} (Eq. 8 with the bunch current)
-        pic::FieldArgs fe = field_args(c, false);
-        tstart(c, 2);
-        pic::launch_e_update(fe, c->stream);
-        tstop(c, 2);
-        c->step++;
-        c->since_sort++;
-        // 5. probes
-        if (c->nprobe > 0) {
-            pic::ProbeArgs pr{};
-            pr.nprobe = c->nprobe;
-            pr.nfreq = c->nfreq;
-            pr.pidx = c->pidx;
-            pr.omega = c->omega;
-            pr.fre = c->fre;
-            pr.fim = c->fim;
-            pr.series = c->series;
-            pr.series_len = c->series_len;
-            pr.step = c->step;
-            pr.dt = c->dt;
-            pr.Ez = c->E[2];
-            pr.nan_flag = c->d_nan;
-            tstart(c, 3);
-            pic::launch_probe(pr, c->stream);
-            tstop(c, 3);
-        }
-        HIP_TRY(c, hipGetLastError());
+        TRY(step_once(c));
         if (c->check_every > 0 && c->step % c->check_every == 0) {
             int flag = 0;
             HIP_TRY(c, hipMemcpyAsync(&flag, c->d_nan, 4, hipMemcpyDeviceToHost, c->stream));
@@ -871,6 +879,233 @@ pic_status pic_timing(pic_ctx *c, double *ms_total, int64_t *launches, int reset
         }
     }
     return PIC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched simulations: one launch per kernel family for all members, and a
+// whole sort period captured once as a HIP graph.
+// ---------------------------------------------------------------------------
+struct pic_batch {
+    std::vector<pic_ctx *> ctx;
+    hipStream_t stream = nullptr;  // the batch's own stream (capturable)
+    hipStream_t ext = nullptr;     // the members' stream
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    pic::FieldArgs *d_fa = nullptr;
+    pic::PartArgs *d_pa = nullptr;
+    pic::ProbeArgs *d_pr = nullptr;
+    int *d_tiles = nullptr, *d_pblocks = nullptr;
+    int total_tiles = 0, total_pblocks = 0;
+    int push_mode = 0;  // bit 0: per-lane atomics, bit 1: some member has a periodic x axis
+    int sort_every = 0;
+    bool particles = false;
+    bool use_graph = false;
+    int graph_steps = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+pic_status bfail(pic_batch *b, pic_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    else g_init_error = buf;
+    return st;
+}
+
+#define BHIP(b, call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return bfail((b), PIC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+void batch_free(pic_batch *b)
+{
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    void *ptrs[5] = {b->d_fa, b->d_pa, b->d_pr, b->d_tiles, b->d_pblocks};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+}
+
+// The four batched launches of one step (sorts are issued separately).
+void batch_launches(pic_batch *b)
+{
+    const int n = (int)b->ctx.size();
+    pic::launch_h_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, b->stream);
+    if (b->particles)
+        pic::launch_push_deposit_batch(b->d_pa, b->d_pblocks, n, b->total_pblocks, b->push_mode, b->stream);
+    pic::launch_e_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, b->stream);
+    pic::launch_probe_batch(b->d_pr, n, b->stream);
+}
+
+void batch_mirror_step(pic_batch *b)
+{
+    for (pic_ctx *c : b->ctx) {
+        c->hcur = 1 - c->hcur;
+        c->step++;
+        c->since_sort++;
+    }
+}
+
+pic_status batch_sorts(pic_batch *b, bool only_due)
+{
+    for (pic_ctx *c : b->ctx) {
+        if (c->np <= 0 || c->sort_every <= 0) continue;
+        if (only_due && c->since_sort < c->sort_every) continue;
+        pic::launch_sort(c->sa, c->scan_tmp, b->stream);
+        c->pcur = 1 - c->pcur;
+        c->since_sort = 0;
+    }
+    BHIP(b, hipGetLastError());
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t n, int32_t use_graph)
+{
+    std::vector<pic::FieldArgs> fa(n);
+    std::vector<pic::PartArgs> pa(n);
+    std::vector<pic::ProbeArgs> pr(n);
+    std::vector<int> tiles(n + 1, 0), pblk(n + 1, 0);
+    for (int q = 0; q < n; ++q) {
+        pic_ctx *c = ctxs[q];
+        if (!c || c->poisoned) return bfail(b, PIC_EINVAL, "context %d is NULL or poisoned", q);
+        for (int r = 0; r < q; ++r)
+            if (ctxs[r] == c) return bfail(b, PIC_EINVAL, "context %d appears twice", q);
+        if (q > 0 && c->stream != ctxs[0]->stream)
+            return bfail(b, PIC_EINVAL, "all contexts must share one stream");
+        if (c->np > 0) {
+            if (b->particles && (c->sort_every != b->sort_every || (b->push_mode & 1) != c->deposit_mode))
+                return bfail(b, PIC_EINVAL, "contexts with particles must share sort_every and deposit_mode");
+            b->particles = true;
+            b->sort_every = c->sort_every;
+            b->push_mode = (b->push_mode & 2) | c->deposit_mode;
+            if (c->per[0]) b->push_mode |= 2;
+        }
+        b->ctx.push_back(c);
+        fa[q] = c->fa;
+        pa[q] = c->pa;
+        pr[q] = c->pr;
+        tiles[q + 1] = tiles[q] + pic::field_tiles(c->n[0], c->n[1], c->n[2]);
+        pblk[q + 1] = pblk[q] + (c->np + pic::PBLOCK - 1) / pic::PBLOCK;
+    }
+    b->ext = ctxs[0]->stream;
+    // an own stream: the members' stream may be the null stream, which cannot be captured
+    BHIP(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    BHIP(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    BHIP(b, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    b->total_tiles = tiles[n];
+    b->total_pblocks = pblk[n];
+    BHIP(b, hipMalloc(&b->d_fa, sizeof(pic::FieldArgs) * n));
+    BHIP(b, hipMalloc(&b->d_pa, sizeof(pic::PartArgs) * n));
+    BHIP(b, hipMalloc(&b->d_pr, sizeof(pic::ProbeArgs) * n));
+    BHIP(b, hipMalloc(&b->d_tiles, sizeof(int) * (n + 1)));
+    BHIP(b, hipMalloc(&b->d_pblocks, sizeof(int) * (n + 1)));
+    BHIP(b, hipMemcpy(b->d_fa, fa.data(), sizeof(pic::FieldArgs) * n, hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_pa, pa.data(), sizeof(pic::PartArgs) * n, hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_pr, pr.data(), sizeof(pic::ProbeArgs) * n, hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_tiles, tiles.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_pblocks, pblk.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    b->use_graph = use_graph != 0;
+    if (b->use_graph) {
+        // one sort period: sort_every steps, then the sorts (since_sort is 0 at
+        // the start of every replay); fields-only batches capture 10 steps
+        b->graph_steps = (b->particles && b->sort_every > 0) ? b->sort_every : 10;
+        BHIP(b, hipStreamSynchronize(b->ext));
+        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        for (int s2 = 0; s2 < b->graph_steps; ++s2) batch_launches(b);
+        if (b->particles && b->sort_every > 0)
+            for (pic_ctx *c : b->ctx)
+                if (c->np > 0) pic::launch_sort(c->sa, c->scan_tmp, b->stream);
+        hipError_t e = hipStreamEndCapture(b->stream, &b->graph);  // always leave capture mode
+        if (e != hipSuccess) return bfail(b, PIC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    return PIC_OK;
+}
+
+pic_status pic_batch_create(pic_batch **out, pic_ctx *const *ctxs, int32_t n, int32_t use_graph)
+{
+    if (!out) return bfail(nullptr, PIC_EINVAL, "batch is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1 || n > 64) return bfail(nullptr, PIC_EINVAL, "need 1..64 contexts");
+    pic_batch *b = new (std::nothrow) pic_batch();
+    if (!b) return bfail(nullptr, PIC_ENOMEM, "out of host memory");
+    pic_status st = batch_create_impl(b, ctxs, n, use_graph);
+    if (st != PIC_OK) {
+        g_init_error = b->err;
+        batch_free(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return PIC_OK;
+}
+
+pic_status pic_batch_step(pic_batch *b, int64_t nsteps)
+{
+    if (!b) return bfail(nullptr, PIC_EINVAL, "batch is NULL");
+    if (nsteps < 0) return bfail(b, PIC_EINVAL, "nsteps must be >= 0");
+    for (pic_ctx *c : b->ctx)
+        if (c->poisoned) return bfail(b, PIC_ESTATE, "a member context is poisoned");
+    // order the batch's stream after, and the members' stream behind, this work
+    BHIP(b, hipEventRecord(b->ev_in, b->ext));
+    BHIP(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    while (nsteps > 0) {
+        bool aligned = true;
+        for (pic_ctx *c : b->ctx)
+            aligned = aligned && (c->np == 0 || c->sort_every == 0 || c->since_sort == 0);
+        if (b->use_graph && aligned && nsteps >= b->graph_steps) {
+            BHIP(b, hipGraphLaunch(b->exec, b->stream));
+            for (int s2 = 0; s2 < b->graph_steps; ++s2) batch_mirror_step(b);
+            if (b->particles && b->sort_every > 0)
+                for (pic_ctx *c : b->ctx)
+                    if (c->np > 0) {
+                        c->pcur = 1 - c->pcur;
+                        c->since_sort = 0;
+                    }
+            nsteps -= b->graph_steps;
+            continue;
+        }
+        pic_status st = batch_sorts(b, true);
+        if (st != PIC_OK) return st;
+        batch_launches(b);
+        BHIP(b, hipGetLastError());
+        batch_mirror_step(b);
+        --nsteps;
+    }
+    BHIP(b, hipEventRecord(b->ev_out, b->stream));
+    BHIP(b, hipStreamWaitEvent(b->ext, b->ev_out, 0));
+    return PIC_OK;
+}
+
+void pic_batch_destroy(pic_batch *b)
+{
+    if (!b) return;
+    batch_free(b);
+    delete b;
+}
+
+const char *pic_batch_last_error(const pic_batch *b)
+{
+    if (!b) return g_init_error.c_str();
+    return b->err.c_str();
 }
 
 }  // extern "C"

@@ -8,6 +8,14 @@
 //   Jt_pol += cbt E - d Jt_pol,  cbt = 2 (wp dt)^2/(2 + g dt), d = 2 g dt/(2 + g dt),
 // which is Eq. 6 / Eq. 8 of the paper rescaled (the increment form keeps
 // the small damping d exact when rounded to FP32).
+//
+// Everything that changes from step to step (which H buffer is current,
+// steps since the last sort, which particle buffer set is current, the step
+// number) lives in a DevState in device memory and is advanced by the
+// kernels themselves.  The argument blocks are therefore fixed for the life
+// of a simulation, so a sequence of steps can be captured once in a HIP
+// graph, and one launch can serve many simulations (an array of argument
+// blocks in device memory).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -15,6 +23,16 @@
 namespace pic {
 
 constexpr int PBLOCK = 256;  // particle kernels
+constexpr int FX = 64;       // field tile: 64 x 4 cells of one z plane
+constexpr int FY = 4;
+
+struct DevState {
+    int parity;      // H[parity] holds H^{n-1/2} at the start of step n
+    int since_sort;  // steps since the last cell sort
+    int pcur;        // particle buffer set in use
+    int pad;
+    long long step;  // steps taken
+};
 
 // CPML data of one axis.  Coefficients are per position along the axis:
 // E-type at node i, H-type at i + 1/2; k* hold 1/kappa.  psi arrays cover
@@ -34,12 +52,12 @@ struct PmlAxis {
 
 struct FieldArgs {
     int nx, ny, nz;
+    int gx, gy;  // tiles along x and y
     int per[3];
     float S;
     float *E[3];
-    const float *Hin[3];
-    float *Hout[3];
-    float *Havg[3];  // H kernel: (Hin + Hout)/2 written inside the particle box, or null
+    float *H[2][3];  // ping-pong: the H update reads H[parity], writes H[parity ^ 1]
+    float *Havg[3];  // (H^{n-1/2} + H^{n+1/2})/2 inside the particle box, or null
     PmlAxis pml[3];
     // Drude polarization current on the metal bounding box [lo, hi)
     int mlo[3], mhi[3];
@@ -47,14 +65,14 @@ struct FieldArgs {
     const float2 *coef;  // (cbt, d) per box cell
     // bunch current: read and cleared inside the particle box (+ margin)
     float *Jb[3];
-    const int *pbox;     // device [6]: lo x,y,z, hi x,y,z (cells, inclusive)
-    int margin;
+    const int *pbox;  // device [6]: lo x,y,z, hi x,y,z (cells, inclusive), or null
     int *nan_flag;
+    DevState *st;
 };
 
 struct PartArgs {
     int n;
-    float *x, *y, *z, *ux, *uy, *uz;
+    float *P[2][6];  // x, y, z, ux, uy, uz for each buffer set
     int nx, ny, nz;
     int per[3];
     const float *E[3];
@@ -64,20 +82,20 @@ struct PartArgs {
     float ah;  // q dt / (2 m c), per V/m
     float qd;  // -q w / (eps0 dx^2), V/m
     unsigned long long *pushes;  // one counter per wavefront: [gridDim * PBLOCK / 64]
+    DevState *st;
 };
 
 struct SortArgs {
     int n;
     int nx, ny, nz;
     int ncell;
-    const float *src[6];
-    float *dst[6];
-    const int *id_src;
-    int *id_dst;
+    float *P[2][6];
+    int *id[2];
     int *key;
     int *rank;
     int *counts;  // [ncell + 1]
     int *box;     // [6] bounding box of live cells, written by the count kernel
+    DevState *st;
 };
 
 struct ProbeArgs {
@@ -87,10 +105,9 @@ struct ProbeArgs {
     double *fre, *fim;
     float *series;        // [series_len * nprobe] or null
     long long series_len;
-    long long step;       // index n of the E^n just computed
     double dt;
     const float *Ez;
-    int *nan_flag;
+    DevState *st;
 };
 
 // A particle is live when every coordinate is finite and inside [0, n) (cell
@@ -101,14 +118,35 @@ __device__ __forceinline__ bool live_pos(float x, float y, float z, int nx, int 
     return x >= 0.f && x < (float)nx && y >= 0.f && y < (float)ny && z >= 0.f && z < (float)nz;
 }
 
+// Cells the particle box is widened by: a particle moves less than S cells
+// per step, and its gather / deposit stencil reaches two cells past its own.
+__device__ __forceinline__ int box_margin(int since_sort, float S)
+{
+    return 3 + (int)ceilf((float)(since_sort + 1) * S);
+}
+
+inline int field_tiles(int nx, int ny, int nz)
+{
+    return ((nx + FX - 1) / FX) * ((ny + FY - 1) / FY) * nz;
+}
+
 // launchers (stream-ordered, no synchronisation)
 void launch_h_update(const FieldArgs &a, hipStream_t s);
 void launch_e_update(const FieldArgs &a, hipStream_t s);
 void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s);
-void launch_probe(const ProbeArgs &a, hipStream_t s);
+void launch_probe(const ProbeArgs &a, hipStream_t s);  // also advances the DevState
 void launch_fill_i32(int *p, int v, long long n, hipStream_t s);
-void launch_sort(const SortArgs &a, int *scan_tmp, int scan_tmp_len, hipStream_t s);
+void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s);
 int scan_tmp_size(int n);
+
+// Batched forms: one launch over many simulations.  `args` is a device array
+// of per-simulation argument blocks; `start` a device prefix table of work
+// units (field tiles / particle workgroups) per simulation, start[n] = total.
+void launch_h_update_batch(const FieldArgs *args, const int *start, int n, int total, hipStream_t s);
+void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int total, hipStream_t s);
+void launch_push_deposit_batch(const PartArgs *args, const int *start, int n, int total, int mode,
+                               hipStream_t s);
+void launch_probe_batch(const ProbeArgs *args, int n, hipStream_t s);
 
 // FP64 diagnostics
 struct DiagArgs {

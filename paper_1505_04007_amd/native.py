@@ -59,7 +59,8 @@ class PicStats(ctypes.Structure):
 
 EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "pic_read_fields",
            "pic_read_particles", "pic_diag", "pic_stats", "pic_timing", "pic_destroy",
-           "pic_last_error")
+           "pic_last_error", "pic_batch_create", "pic_batch_step", "pic_batch_destroy",
+           "pic_batch_last_error")
 
 _LIB = None
 
@@ -106,6 +107,15 @@ def load():
     lib.pic_destroy.argtypes = [vp]
     lib.pic_last_error.restype = ctypes.c_char_p
     lib.pic_last_error.argtypes = [vp]
+    lib.pic_batch_create.restype = ctypes.c_int
+    lib.pic_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32,
+                                     ctypes.c_int32]
+    lib.pic_batch_step.restype = ctypes.c_int
+    lib.pic_batch_step.argtypes = [vp, ctypes.c_int64]
+    lib.pic_batch_destroy.restype = None
+    lib.pic_batch_destroy.argtypes = [vp]
+    lib.pic_batch_last_error.restype = ctypes.c_char_p
+    lib.pic_batch_last_error.argtypes = [vp]
     _LIB = lib
     return lib
 
@@ -281,3 +291,34 @@ def from_workload(w, with_bunch=True, **kw):
     return Simulation(w.nx, w.ny, w.nz, w.dx, w.dt, w.wp_map, w.gamma_map, bc=w.bc, npml=w.npml,
                       pml=w.pml, bunch=w.bunch if with_bunch else None, probes=w.probes,
                       omega=w.omega, sort_every=kw.pop("sort_every", w.sort_every), **kw)
+
+
+class Batch:
+    """Several Simulations advanced together (pic_batch_*): one launch per kernel
+    family per step for all members, optionally replaying a captured HIP graph
+    of one sort period.  The member Simulations stay readable and must outlive
+    the batch."""
+
+    def __init__(self, sims, use_graph=True):
+        self._lib = load()
+        self.sims = list(sims)
+        arr = (ctypes.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
+        h = ctypes.c_void_p()
+        st = self._lib.pic_batch_create(ctypes.byref(h), arr, len(self.sims), int(bool(use_graph)))
+        self._h = None
+        if st != PIC_OK:
+            raise PicError(st, self._lib.pic_batch_last_error(None).decode())
+        self._h = h
+
+    def step(self, n=1):
+        st = self._lib.pic_batch_step(self._h, int(n))
+        if st != PIC_OK:
+            raise PicError(st, self._lib.pic_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -31,6 +31,11 @@
  * minus sign of Eq. 8, beam current in Eq. 8, pusher/deposit scheme, CPML
  * in place of the split-field PML, edge material rule) are the ones listed
  * in the design notes; each is restated at the code that applies it.
+ *
+ * The differentiable form (the gradient of probe spectral power with respect
+ * to the per-cell wp and gamma of Eq. 1) is the plain reverse-time transpose
+ * of steps 1, 3 and 4 with the bunch current of step 2 held at the values a
+ * forward run produced; it is written at the end of this file.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -78,6 +83,15 @@ typedef struct {
     long step;
     double t_field, t_part;
     long pushes;
+    /* bunch current as a prescribed source: presc[(step - presc0) * nJ + ...] */
+    double *presc;
+    long presc_n, presc0;
+    /* adjoint state (reverse-time), same extents as the forward arrays */
+    int adj_on;
+    ofield Ea[3], Ha[3], Ja[3];
+    ofield psiEa[3][3], psiHa[3][3];
+    /* the material maps the coefficients were made from (C order) */
+    double *wp_map, *gamma_map;
 } osim;
 
 static ofield fnew(int a, int b, int c)
@@ -204,6 +218,10 @@ osim *osim_create(int nx, int ny, int nz, const int *bc, int npml, const double 
                                 &AT(s->cb[c], i, j, k));
                 }
     }
+    s->wp_map = malloc(sizeof(double) * (size_t)nx * ny * nz);
+    s->gamma_map = malloc(sizeof(double) * (size_t)nx * ny * nz);
+    memcpy(s->wp_map, wp_map, sizeof(double) * (size_t)nx * ny * nz);
+    memcpy(s->gamma_map, gamma_map, sizeof(double) * (size_t)nx * ny * nz);
     for (int a = 0; a < 3; ++a) {
         int n = s->n[a];
         s->bE[a] = calloc(n + 1, sizeof(double));
@@ -260,6 +278,19 @@ void osim_destroy(osim *s)
     free(s->omega);
     free(s->fre);
     free(s->fim);
+    free(s->presc);
+    free(s->wp_map);
+    free(s->gamma_map);
+    if (s->adj_on)
+        for (int c = 0; c < 3; ++c) {
+            ffree(&s->Ea[c]);
+            ffree(&s->Ha[c]);
+            ffree(&s->Ja[c]);
+            for (int a = 0; a < 3; ++a) {
+                free(s->psiEa[c][a].v);
+                free(s->psiHa[c][a].v);
+            }
+        }
     free(s);
 }
 
@@ -757,13 +788,61 @@ void osim_probe_values(const osim *s, double *out)
         out[p] = AT(s->E[2], s->pijk[3 * p], s->pijk[3 * p + 1], s->pijk[3 * p + 2]);
 }
 
+/* Number of doubles in one J_b snapshot (the three components back to back). */
+long osim_jb_size(const osim *s)
+{
+    return (long)(fsize(&s->Jb[0]) + fsize(&s->Jb[1]) + fsize(&s->Jb[2]));
+}
+
+static void jb_save(const osim *s, double *out)
+{
+    size_t o = 0;
+    for (int c = 0; c < 3; ++c) {
+        memcpy(out + o, s->Jb[c].v, fsize(&s->Jb[c]) * sizeof(double));
+        o += fsize(&s->Jb[c]);
+    }
+}
+
+static void jb_load(osim *s, const double *in)
+{
+    size_t o = 0;
+    for (int c = 0; c < 3; ++c) {
+        memcpy(s->Jb[c].v, in + o, fsize(&s->Jb[c]) * sizeof(double));
+        o += fsize(&s->Jb[c]);
+    }
+}
+
+/*
+ * From now on use the given bunch current J_b^{n+1/2} for the next n steps
+ * instead of pushing particles (the source held fixed by the adjoint).
+ */
+void osim_prescribe_jb(osim *s, const double *hist, long n)
+{
+    free(s->presc);
+    s->presc = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)osim_jb_size(s));
+    memcpy(s->presc, hist, sizeof(double) * (size_t)n * (size_t)osim_jb_size(s));
+    s->presc_n = n;
+    s->presc0 = s->step;
+}
+
+/* Step 2 of the step: particles, or the prescribed bunch current. */
+static void source_step(osim *s)
+{
+    if (s->presc) {
+        long r = s->step - s->presc0;
+        if (r >= 0 && r < s->presc_n) jb_load(s, s->presc + (size_t)r * (size_t)osim_jb_size(s));
+    } else {
+        push_particles(s);
+    }
+}
+
 void osim_step(osim *s, long nsteps)
 {
     for (long it = 0; it < nsteps; ++it) {
         double t0 = now_s();
         update_H(s);
         double t1 = now_s();
-        push_particles(s);
+        source_step(s);
         double t2 = now_s();
         update_E(s);
         s->step++;
@@ -900,4 +979,283 @@ void oracle_constants(double *out)
     out[0] = OR_C;
     out[1] = OR_MU0;
     out[2] = OR_EPS0;
+}
+
+/* ======================================================================
+ * Adjoint (reverse-time) of the field + Drude + CPML step with the bunch
+ * current held fixed, and the gradient of the probe spectral power
+ *   L = sum_p |F_p(w0)|^2,   F_p = sum_{n=1..N} dt Ez_p^n exp(-i w0 n dt)
+ * with respect to the per-cell plasma and collision frequencies (the maps
+ * of Eq. 1).  The step is linear in (E, H, J, psi); its transpose is taken
+ * operation by operation in reverse order.  For a forward update of the form
+ *   psi' = b psi + c d,   t = d / kappa + psi',   X' = X + s t
+ * the adjoint, given Xbar' and psibar' (from later steps), is
+ *   tbar = s Xbar',  psibar_tot = psibar' + tbar,
+ *   dbar = tbar / kappa + c psibar_tot,  psibar = b psibar_tot,
+ * and dbar is scattered onto the two values whose difference is d.
+ * ====================================================================== */
+
+static void adj_alloc(osim *s)
+{
+    if (s->adj_on) return;
+    for (int c = 0; c < 3; ++c) {
+        s->Ea[c] = fnew(s->E[c].n[0], s->E[c].n[1], s->E[c].n[2]);
+        s->Ja[c] = fnew(s->E[c].n[0], s->E[c].n[1], s->E[c].n[2]);
+        s->Ha[c] = fnew(s->H[c].n[0], s->H[c].n[1], s->H[c].n[2]);
+        for (int a = 0; a < 3; ++a) {
+            s->psiEa[c][a] = s->psiE[c][a].v ? fnew(s->E[c].n[0], s->E[c].n[1], s->E[c].n[2]) : (ofield){{0, 0, 0}, NULL};
+            s->psiHa[c][a] = s->psiH[c][a].v ? fnew(s->H[c].n[0], s->H[c].n[1], s->H[c].n[2]) : (ofield){{0, 0, 0}, NULL};
+        }
+    }
+    s->adj_on = 1;
+}
+
+void osim_adj_zero(osim *s)
+{
+    adj_alloc(s);
+    for (int c = 0; c < 3; ++c) {
+        memset(s->Ea[c].v, 0, fsize(&s->Ea[c]) * sizeof(double));
+        memset(s->Ja[c].v, 0, fsize(&s->Ja[c]) * sizeof(double));
+        memset(s->Ha[c].v, 0, fsize(&s->Ha[c]) * sizeof(double));
+        for (int a = 0; a < 3; ++a) {
+            if (s->psiEa[c][a].v) memset(s->psiEa[c][a].v, 0, fsize(&s->psiEa[c][a]) * sizeof(double));
+            if (s->psiHa[c][a].v) memset(s->psiHa[c][a].v, 0, fsize(&s->psiHa[c][a]) * sizeof(double));
+        }
+    }
+}
+
+/*
+ * Raw access: which 0 = E-bar, 1 = H-bar, 2 = J-bar (comp c), 3 = psi_E,
+ * 4 = psi_H, 5 = psi_E-bar, 6 = psi_H-bar (comp c, derivative axis a).
+ * NULL when the array does not exist.
+ */
+double *osim_adj_ptr(osim *s, int which, int c, int a, int *ext)
+{
+    adj_alloc(s);
+    ofield *f = NULL;
+    switch (which) {
+    case 0: f = &s->Ea[c]; break;
+    case 1: f = &s->Ha[c]; break;
+    case 2: f = &s->Ja[c]; break;
+    case 3: f = &s->psiE[c][a]; break;
+    case 4: f = &s->psiH[c][a]; break;
+    case 5: f = &s->psiEa[c][a]; break;
+    case 6: f = &s->psiHa[c][a]; break;
+    default: return NULL;
+    }
+    for (int d = 0; d < 3; ++d) ext[d] = f->n[d];
+    return f->v;
+}
+
+/* One adjoint CPML term: returns dbar and updates psibar in place. */
+static double adj_pml(double tbar, double *psibar, double b, double c, double kap)
+{
+    const double tot = *psibar + tbar;
+    *psibar = b * tot;
+    return tbar / kap + c * tot;
+}
+
+/* Index of node/half-position i along a periodic axis. */
+static int pw(const osim *s, int a, int i) { return s->bc[a] == OR_PERIODIC ? wrap(s, a, i) : i; }
+
+/* Reverse of the periodic copy node n <- node 0 made after each E update. */
+static void adj_fold_periodic(osim *s)
+{
+    for (int c = 0; c < 3; ++c) {
+        ofield f = s->Ea[c];
+        for (int a = 0; a < 3; ++a) {
+            if (a == c || s->bc[a] != OR_PERIODIC) continue;
+            int n = s->n[a];
+            for (int i = 0; i < f.n[0]; ++i)
+                for (int j = 0; j < f.n[1]; ++j)
+                    for (int k = 0; k < f.n[2]; ++k) {
+                        int id[3] = {i, j, k};
+                        if (id[a] != n) continue;
+                        double v = AT(f, i, j, k);
+                        AT(f, i, j, k) = 0.0;
+                        id[a] = 0;
+                        AT(f, id[0], id[1], id[2]) += v;
+                    }
+        }
+    }
+}
+
+/*
+ * Reverse of steps 3+4 (Eq. 6 then Eq. 8).  En, Jn: E^n and J^{n-1/2} of the
+ * forward run (same layout as the E arrays, components back to back); gca,
+ * gcb accumulate dL/dca and dL/dcb per edge (NULL: no gradient).
+ */
+static void adj_update_E(osim *s, const double *En, const double *Jn, double *gca, double *gcb)
+{
+    const double ce = s->dt / (OR_EPS0 * s->dx);
+    const double cj = s->dt / OR_EPS0;
+    size_t off = 0;
+    for (int c = 0; c < 3; ++c) {
+        ofield E = s->Ea[c];
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;  /* curl: + d/d(a1) of H(a2), - d/d(a2) of H(a1) */
+        for (int i = 0; i < E.n[0]; ++i)
+            for (int j = 0; j < E.n[1]; ++j)
+                for (int k = 0; k < E.n[2]; ++k) {
+                    int id[3] = {i, j, k};
+                    if (!e_node_updated(s, a1, id[a1]) || !e_node_updated(s, a2, id[a2])) continue;
+                    const double ab = AT(E, i, j, k);
+                    /* + (H_a2(id) - H_a2(id - e_a1)) */
+                    double t1 = ce * ab;
+                    if (s->lE[a1][id[a1]])
+                        t1 = adj_pml(t1, &AT(s->psiEa[c][a1], i, j, k), s->bE[a1][id[a1]], s->cE[a1][id[a1]], s->kE[a1][id[a1]]);
+                    /* - (H_a1(id) - H_a1(id - e_a2)) */
+                    double t2 = -ce * ab;
+                    if (s->lE[a2][id[a2]])
+                        t2 = adj_pml(t2, &AT(s->psiEa[c][a2], i, j, k), s->bE[a2][id[a2]], s->cE[a2][id[a2]], s->kE[a2][id[a2]]);
+                    int m1[3] = {i, j, k}, m2[3] = {i, j, k};
+                    m1[a1] = pw(s, a1, id[a1] - 1);
+                    m2[a2] = pw(s, a2, id[a2] - 1);
+                    AT(s->Ha[a2], i, j, k) += t1;
+                    AT(s->Ha[a2], m1[0], m1[1], m1[2]) -= t1;
+                    AT(s->Ha[a1], i, j, k) += t2;
+                    AT(s->Ha[a1], m2[0], m2[1], m2[2]) -= t2;
+                    /* J^{n+1/2} enters as - (dt/eps0) J; J^{n+1/2} = ca J^{n-1/2} + cb E^n */
+                    const double jt = AT(s->Ja[c], i, j, k) - cj * ab;
+                    const size_t q = off + ((size_t)i * E.n[1] + j) * E.n[2] + k;
+                    if (gca) {
+                        gca[q] += jt * Jn[q];
+                        gcb[q] += jt * En[q];
+                    }
+                    AT(s->Ja[c], i, j, k) = AT(s->ca[c], i, j, k) * jt;
+                    AT(E, i, j, k) = ab + AT(s->cb[c], i, j, k) * jt;
+                }
+        off += fsize(&s->E[c]);
+    }
+}
+
+/* Reverse of step 1: H^{n+1/2} = H^{n-1/2} - (dt/mu0) curl E^n. */
+static void adj_update_H(osim *s)
+{
+    const double ch = s->dt / (OR_MU0 * s->dx);
+    for (int c = 0; c < 3; ++c) {
+        ofield H = s->Ha[c];
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;  /* curl: + d/d(a1) of E(a2), - d/d(a2) of E(a1) */
+        for (int i = 0; i < H.n[0]; ++i)
+            for (int j = 0; j < H.n[1]; ++j)
+                for (int k = 0; k < H.n[2]; ++k) {
+                    int id[3] = {i, j, k};
+                    const double ab = AT(H, i, j, k);
+                    /* H -= ch ( (E_a2(id + e_a1) - E_a2(id)) - (E_a1(id + e_a2) - E_a1(id)) ) */
+                    double t1 = -ch * ab;
+                    if (s->lH[a1][id[a1]])
+                        t1 = adj_pml(t1, &AT(s->psiHa[c][a1], i, j, k), s->bH[a1][id[a1]], s->cH[a1][id[a1]], s->kH[a1][id[a1]]);
+                    double t2 = ch * ab;
+                    if (s->lH[a2][id[a2]])
+                        t2 = adj_pml(t2, &AT(s->psiHa[c][a2], i, j, k), s->bH[a2][id[a2]], s->cH[a2][id[a2]], s->kH[a2][id[a2]]);
+                    int p1[3] = {i, j, k}, p2[3] = {i, j, k};
+                    p1[a1] += 1;
+                    p2[a2] += 1;
+                    AT(s->Ea[a2], p1[0], p1[1], p1[2]) += t1;
+                    AT(s->Ea[a2], i, j, k) -= t1;
+                    AT(s->Ea[a1], p2[0], p2[1], p2[2]) += t2;
+                    AT(s->Ea[a1], i, j, k) -= t2;
+                }
+    }
+}
+
+/* Transpose of one field step (J_b fixed, no probes, no gradient). */
+void osim_adj_step(osim *s)
+{
+    adj_alloc(s);
+    adj_fold_periodic(s);
+    adj_update_E(s, NULL, NULL, NULL, NULL);
+    adj_update_H(s);
+}
+
+/* Run n steps from the current state and write J_b^{n+1/2} of each (n x jb_size). */
+void osim_run_record_jb(osim *s, long n, double *out)
+{
+    const size_t nj = (size_t)osim_jb_size(s);
+    for (long it = 0; it < n; ++it) {
+        update_H(s);
+        source_step(s);
+        jb_save(s, out + (size_t)it * nj);
+        update_E(s);
+        s->step++;
+        sample_probes(s);
+    }
+}
+
+/*
+ * Forward N steps from the current state (particles, or the prescribed
+ * current), then the adjoint back to the start; L and the gradients (per
+ * cell, C order like the maps) with the bunch current held at what the
+ * forward run produced.  Needs at least one probe.
+ */
+void osim_grad(osim *s, long N, double w0, double *L, double *g_wp, double *g_gamma)
+{
+    const int np = s->nprobe;
+    size_t nE = 0;
+    for (int c = 0; c < 3; ++c) nE += fsize(&s->E[c]);
+    double *hE = malloc(sizeof(double) * nE * (size_t)(N > 0 ? N : 1));
+    double *hJ = malloc(sizeof(double) * nE * (size_t)(N > 0 ? N : 1));
+    double *Fr = calloc((size_t)np + 1, sizeof(double)), *Fi = calloc((size_t)np + 1, sizeof(double));
+    const long step0 = s->step;
+    for (long n = 0; n < N; ++n) {
+        size_t o = 0;
+        for (int c = 0; c < 3; ++c) {
+            memcpy(hE + (size_t)n * nE + o, s->E[c].v, fsize(&s->E[c]) * sizeof(double));
+            memcpy(hJ + (size_t)n * nE + o, s->J[c].v, fsize(&s->J[c]) * sizeof(double));
+            o += fsize(&s->E[c]);
+        }
+        osim_step(s, 1);
+        const double th = w0 * (double)s->step * s->dt;
+        for (int p = 0; p < np; ++p) {
+            const double ez = AT(s->E[2], s->pijk[3 * p], s->pijk[3 * p + 1], s->pijk[3 * p + 2]);
+            Fr[p] += s->dt * ez * cos(th);
+            Fi[p] -= s->dt * ez * sin(th);
+        }
+    }
+    double l = 0.0;
+    for (int p = 0; p < np; ++p) l += Fr[p] * Fr[p] + Fi[p] * Fi[p];
+    *L = l;
+
+    osim_adj_zero(s);
+    double *gca = calloc(nE, sizeof(double)), *gcb = calloc(nE, sizeof(double));
+    for (long n = N - 1; n >= 0; --n) {
+        /* dL/dEz_p^{n+1} = 2 dt (Re F cos th - Im F sin th) */
+        const double th = w0 * (double)(step0 + n + 1) * s->dt;
+        for (int p = 0; p < np; ++p)
+            AT(s->Ea[2], s->pijk[3 * p], s->pijk[3 * p + 1], s->pijk[3 * p + 2]) +=
+                2.0 * s->dt * (Fr[p] * cos(th) - Fi[p] * sin(th));
+        adj_fold_periodic(s);
+        adj_update_E(s, hE + (size_t)n * nE, hJ + (size_t)n * nE, gca, gcb);
+        adj_update_H(s);
+    }
+    /* chain rule to (wp, gamma) of the owning cell (lower-corner rule) */
+    memset(g_wp, 0, sizeof(double) * (size_t)s->n[0] * s->n[1] * s->n[2]);
+    memset(g_gamma, 0, sizeof(double) * (size_t)s->n[0] * s->n[1] * s->n[2]);
+    const double dt = s->dt;
+    size_t off = 0;
+    for (int c = 0; c < 3; ++c) {
+        ofield E = s->E[c];
+        for (int i = 0; i < E.n[0]; ++i)
+            for (int j = 0; j < E.n[1]; ++j)
+                for (int k = 0; k < E.n[2]; ++k) {
+                    const size_t q = off + ((size_t)i * E.n[1] + j) * E.n[2] + k;
+                    if (gca[q] == 0.0 && gcb[q] == 0.0) continue;
+                    const int ci = clampi(i, s->n[0]), cj = clampi(j, s->n[1]), ck = clampi(k, s->n[2]);
+                    const size_t m = cidx(s, ci, cj, ck);
+                    const double wp = s->wp_map[m], g = s->gamma_map[m];
+                    const double den = 2.0 + g * dt;
+                    /* derivatives of the Eq. 6 coefficients */
+                    const double dca_dg = -4.0 * dt / (den * den);
+                    const double dcb_dwp = 4.0 * dt * OR_EPS0 * wp / den;
+                    const double dcb_dg = -2.0 * dt * dt * OR_EPS0 * wp * wp / (den * den);
+                    g_wp[m] += gcb[q] * dcb_dwp;
+                    g_gamma[m] += gca[q] * dca_dg + gcb[q] * dcb_dg;
+                }
+        off += fsize(&E);
+    }
+    free(gca);
+    free(gcb);
+    free(hE);
+    free(hJ);
+    free(Fr);
+    free(Fi);
 }

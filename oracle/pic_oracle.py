@@ -56,6 +56,16 @@ def _load():
     lib.osim_diag.argtypes = [ctypes.c_void_p, _dp]
     lib.osim_timing.argtypes = [ctypes.c_void_p, _dp]
     lib.oracle_constants.argtypes = [_dp]
+    lib.osim_jb_size.restype = ctypes.c_long
+    lib.osim_jb_size.argtypes = [ctypes.c_void_p]
+    lib.osim_prescribe_jb.argtypes = [ctypes.c_void_p, _dp, ctypes.c_long]
+    lib.osim_run_record_jb.argtypes = [ctypes.c_void_p, ctypes.c_long, _dp]
+    lib.osim_adj_zero.argtypes = [ctypes.c_void_p]
+    lib.osim_adj_step.argtypes = [ctypes.c_void_p]
+    lib.osim_adj_ptr.restype = _dp
+    lib.osim_adj_ptr.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int)]
+    lib.osim_grad.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_double, _dp, _dp, _dp]
     _LIB = lib
     return lib
 
@@ -217,3 +227,61 @@ class OracleSim:
         self._lib.osim_timing(self._h, _p(out))
         return {"field_s": out[0], "particle_s": out[1], "pushes": int(out[2]),
                 "threads": int(out[3])}
+
+    # ---- bunch current as a prescribed source, and the adjoint ----
+    def jb_size(self):
+        """Doubles in one J_b snapshot (the three E-edge arrays back to back)."""
+        return int(self._lib.osim_jb_size(self._h))
+
+    def run_record_jb(self, n):
+        """Step n times and return J_b^{n+1/2} of each step, shape (n, jb_size)."""
+        out = np.zeros((int(n), self.jb_size()))
+        self._lib.osim_run_record_jb(self._h, int(n), _p(out))
+        return out
+
+    def prescribe_jb(self, hist):
+        """Use hist[r] as the bunch current of the r-th next step (no particle push)."""
+        hist = _f64(hist)
+        assert hist.ndim == 2 and hist.shape[1] == self.jb_size()
+        self._lib.osim_prescribe_jb(self._h, _p(hist), hist.shape[0])
+
+    def _adj(self, which, c, a=0):
+        ext = (ctypes.c_int * 3)()
+        ptr = self._lib.osim_adj_ptr(self._h, which, c, a, ext)
+        if not ptr:
+            return None
+        return np.ctypeslib.as_array(ptr, shape=tuple(ext))
+
+    @property
+    def Ea(self):
+        return [self._adj(0, c) for c in range(3)]
+
+    @property
+    def Ha(self):
+        return [self._adj(1, c) for c in range(3)]
+
+    @property
+    def Ja(self):
+        return [self._adj(2, c) for c in range(3)]
+
+    def psi(self, field, c, a, adjoint=False):
+        """CPML memory of component c along axis a ('E' or 'H'); None if absent."""
+        which = {"E": 3, "H": 4}[field] + (2 if adjoint else 0)
+        return self._adj(which, c, a)
+
+    def adj_zero(self):
+        self._lib.osim_adj_zero(self._h)
+
+    def adj_step(self):
+        """Apply the transpose of one field step (bunch current fixed) to the adjoint state."""
+        self._lib.osim_adj_step(self._h)
+
+    def grad(self, nsteps, omega0):
+        """Run nsteps forward, then the adjoint back.  Returns (L, dL/dwp, dL/dgamma)
+        for L = sum over probes of |F_p(omega0)|^2, with the bunch current held at
+        the values of this forward run."""
+        L = np.zeros(1)
+        gw = np.zeros(self.n)
+        gg = np.zeros(self.n)
+        self._lib.osim_grad(self._h, int(nsteps), float(omega0), _p(L), _p(gw), _p(gg))
+        return float(L[0]), gw, gg

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1
+#define PIC_ABI_VERSION 2
 
 typedef enum {
     PIC_OK = 0,
@@ -168,12 +168,37 @@ pic_status pic_step(pic_ctx *ctx, int64_t nsteps);
 pic_status pic_probe(pic_ctx *ctx, double *re, double *im, double *series);
 
 /*
- * Gradient of the probe spectral power L = sum_p |F_p(omega0)|^2 with
- * respect to the per-cell wp and gamma maps, by a reverse-time adjoint of
- * the field + Drude step with the bunch current held fixed.
- * Returns PIC_ENOTSUP in this version of the library.
+ * Gradient of the probe spectral power with respect to the Drude maps of
+ * Eq. 1 (the differentiable form of the Sec. II step).
+ *
+ * Advances the simulation by nsteps steps exactly as pic_step would (the
+ * context ends in the same state, probe spectra included) and returns
+ *   L = sum_p |F_p|^2,  F_p = sum_{n = s0+1}^{s0+nsteps} dt Ez_p^n exp(-i omega0 n dt)
+ * (s0 = steps taken before the call; the probes are those given at
+ * pic_init) and, per cell, dL/dwp and dL/dgamma with the bunch current held
+ * at the values this run deposits (the current is recorded and prescribed;
+ * the field's back-action on the bunch is not differentiated).
+ *
+ * Method: the forward run stores a field checkpoint every ckpt_every steps
+ * (0: ceil(sqrt(nsteps))) and the bunch current of every step on its
+ * particle box; the reverse pass replays each segment from its checkpoint
+ * with the recorded current and runs the transposed field + Drude + CPML
+ * step back through it, accumulating the gradient in FP64.  Device memory
+ * is allocated for the call and released before it returns: about
+ * (nsteps/ckpt_every + 1) field states, the recorded current, ckpt_every
+ * metal-box snapshots and one adjoint field state.
+ *
+ *   omega0     : rad/s
+ *   L          : out, V^2 s^2 / m^2
+ *   dL_dwp     : out [nx*ny*nz] (same layout as wp_map), per rad/s; may be NULL
+ *   dL_dgamma  : out [nx*ny*nz], per 1/s; may be NULL
+ * Both maps are 0 outside cells with wp > 0.  Synchronises the stream.
+ * Errors: PIC_EINVAL (nsteps < 1, ckpt_every < 0, no probes, L NULL,
+ * omega0 not finite), PIC_ENOMEM, PIC_EDEVICE, PIC_EUNSTABLE.  After an
+ * error other than PIC_EINVAL the simulation may stand at any step of the
+ * call's forward run.
  */
-pic_status pic_grad(pic_ctx *ctx, double omega0, int64_t nsteps, double *L,
+pic_status pic_grad(pic_ctx *ctx, double omega0, int64_t nsteps, int64_t ckpt_every, double *L,
                     double *dL_dwp, double *dL_dgamma);
 
 /* Copy one field (3 components, compact Yee layout, SI units) to host. */

@@ -10,7 +10,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["pic_abi.hip", "kernels_fields.hip", "kernels_particles.hip", "kernels_diag.hip"]
+SOURCES = ["pic_abi.hip", "kernels_fields.hip", "kernels_particles.hip", "kernels_diag.hip",
+           "kernels_adjoint.hip"]
 LIB = os.path.join(PKG, "libpic.so")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -23,6 +23,8 @@ __device__ __forceinline__ void probe_body(const ProbeArgs &a)
     }
     if (a.series && t < a.nprobe && n1 - 1 < a.series_len)
         a.series[(n1 - 1) * a.nprobe + t] = a.Ez[a.pidx[t]];
+    if (a.gser && t < a.nprobe && n1 > a.g0 && n1 <= a.g0 + a.gn)
+        a.gser[(n1 - a.g0 - 1) * a.nprobe + t] = (double)a.Ez[a.pidx[t]];
     __syncthreads();  // every thread has read the clock before it moves
     if (t == 0) {
         DevState *st = a.st;

@@ -26,28 +26,6 @@ __device__ __forceinline__ int lin(const FieldArgs &a, int i, int j, int k)
     return i + a.nx * (j + a.ny * k);
 }
 
-// Linear offset to the neighbour at distance d = +-1 along an axis of n
-// cells with stride st: wraps on a periodic axis; across a wall it points
-// at the cell itself and clears `ok` (the neighbour value is then 0).
-__device__ __forceinline__ int nb_off(int i, int d, int n, int per, int st, bool &ok)
-{
-    const int r = i + d;
-    const bool in = r >= 0 && r < n;
-    ok = in || per;
-    const int w = r < 0 ? r + n : r - n;
-    return in ? d * st : (per ? (w - i) * st : 0);
-}
-
-// Workgroup -> tile with XCD locality: the 8 XCDs receive workgroups round
-// robin, so workgroup b runs on XCD b % 8; give each XCD a contiguous block
-// of tiles.
-__device__ __forceinline__ int xcd_tile()
-{
-    const int B = gridDim.x;
-    const int b = blockIdx.x;
-    return (B % 8 == 0) ? (b % 8) * (B / 8) + b / 8 : b;
-}
-
 __device__ __forceinline__ float cpml(float *__restrict__ psi, int sid, float b, float c, float ik,
                                       float d)
 {
@@ -56,7 +34,6 @@ __device__ __forceinline__ float cpml(float *__restrict__ psi, int sid, float b,
     return d * ik + s;
 }
 
-__device__ __forceinline__ int slab_p(int q, int n, int np) { return q < np ? q : q - (n - 2 * np); }
 
 // Inside the live-particle cell box of the last sort widened by the margin
 // (every cell a particle can gather from or deposit to this step); a

@@ -39,8 +39,10 @@ struct DevState {
 // the two absorbing slabs (2*npml planes) of that axis:
 //   x: idx = p + 2npml*(j + ny*k)   y: idx = i + nx*(p + 2npml*k)
 //   z: idx = i + nx*(j + ny*p),     p = q < npml ? q : q - (n - 2npml).
-// psi[a][0] / psi[a][1] belong to the lower / higher numbered component
-// that is differentiated along a (x: y,z   y: x,z   z: x,y).
+// psi[a][0] / psi[a][1] belong to the lower / higher numbered updated
+// component whose curl differentiates along a (x: y,z   y: x,z   z: x,y):
+// psiE[x][0] is the memory of dHz/dx in the Ey update, psiH[z][1] that of
+// dEx/dz in the Hy update, and so on.
 struct PmlAxis {
     int on;
     int npml;
@@ -107,6 +109,10 @@ struct ProbeArgs {
     long long series_len;
     double dt;
     const float *Ez;
+    // optional FP64 record of Ez at the probes for steps g0+1 .. g0+gn
+    // (gser[(n - g0 - 1) * nprobe + p]), used by the gradient's objective
+    double *gser;
+    long long g0, gn;
     DevState *st;
 };
 
@@ -130,6 +136,31 @@ inline int field_tiles(int nx, int ny, int nz)
     return ((nx + FX - 1) / FX) * ((ny + FY - 1) / FY) * nz;
 }
 
+// Linear offset to the neighbour at distance d = +-1 along an axis of n
+// cells with stride st: wraps on a periodic axis; across a wall it points
+// at the cell itself and clears `ok` (the neighbour value is then 0).
+__device__ __forceinline__ int nb_off(int i, int d, int n, int per, int st, bool &ok)
+{
+    const int r = i + d;
+    const bool in = r >= 0 && r < n;
+    ok = in || per;
+    const int w = r < 0 ? r + n : r - n;
+    return in ? d * st : (per ? (w - i) * st : 0);
+}
+
+// Workgroup -> tile with XCD locality: the 8 XCDs receive workgroups round
+// robin, so workgroup b runs on XCD b % 8; give each XCD a contiguous block
+// of tiles.
+__device__ __forceinline__ int xcd_tile()
+{
+    const int B = gridDim.x;
+    const int b = blockIdx.x;
+    return (B % 8 == 0) ? (b % 8) * (B / 8) + b / 8 : b;
+}
+
+// Position of plane q inside the two absorbing slabs of an axis.
+__device__ __forceinline__ int slab_p(int q, int n, int np) { return q < np ? q : q - (n - 2 * np); }
+
 // launchers (stream-ordered, no synchronisation)
 void launch_h_update(const FieldArgs &a, hipStream_t s);
 void launch_e_update(const FieldArgs &a, hipStream_t s);
@@ -147,6 +178,57 @@ void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int t
 void launch_push_deposit_batch(const PartArgs *args, const int *start, int n, int total, int mode,
                                hipStream_t s);
 void launch_probe_batch(const ProbeArgs *args, int n, hipStream_t s);
+
+// ---- reverse-time adjoint of the linear field step (bunch current fixed) ----
+//
+// Adjoint state in the same normalised units and compact layout as the
+// forward fields: Ea = dL/dE, Ha = dL/dHt, Ja = dL/dJt_pol (metal box);
+// psiEa / psiHa are the adjoint CPML memories (same slab layout as psiE /
+// psiH), DE / DH per-step scratch holding the adjoint weight of each slab
+// difference.
+struct AdjArgs {
+    int nx, ny, nz;
+    int gx, gy;
+    int per[3];
+    float S;
+    float *Ea[3];
+    float *Ha[3];
+    PmlAxis pml[3];  // forward coefficient tables (b, c, 1/kappa) and slab sizes
+    float *psiEa[3][2], *psiHa[3][2];
+    float *DE[3][2], *DH[3][2];
+    int mlo[3], mhi[3];
+    float *Ja[3];
+    const float2 *coef;  // (cbt, d) per metal-box cell
+    const float *traj;   // this step's E^n (3 comps) then Jt^{n-1/2} (3 comps), metal box
+    double *gcb, *gd;    // per metal-box cell: dL/dcbt and dL/dd summed over its edges
+    int nprobe;
+    const int *pidx;
+    const float *seed;   // dL/dEz at the probes for E^n, or null
+    int mode;            // bit 0: reverse the step; bit 1: add seed and prepare the CPML weights
+};
+
+// Copy of a box [lo, lo + w) of three grid arrays to / from a packed buffer.
+struct BoxCopyArgs {
+    float *grid[3];
+    float *packed;  // [3][w0*w1*w2], x fastest
+    int nx, ny;
+    int lo[3], w[3];
+    int to_grid;
+};
+
+// Forward values the gradient needs at step n on the metal box.
+struct TrajArgs {
+    const float *E[3];
+    const float *Jp[3];
+    float *out;  // [6][nbox]
+    int nx, ny;
+    int mlo[3], w[3];
+};
+
+void launch_adj_face(const AdjArgs &a, hipStream_t s);
+void launch_adj_edge(const AdjArgs &a, hipStream_t s);
+void launch_box_copy(const BoxCopyArgs &a, hipStream_t s);
+void launch_traj_store(const TrajArgs &a, hipStream_t s);
 
 // FP64 diagnostics
 struct DiagArgs {

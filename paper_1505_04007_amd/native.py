@@ -92,7 +92,7 @@ def load():
     lib.pic_probe.restype = ctypes.c_int
     lib.pic_probe.argtypes = [vp, _dp, _dp, _dp]
     lib.pic_grad.restype = ctypes.c_int
-    lib.pic_grad.argtypes = [vp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp]
+    lib.pic_grad.argtypes = [vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
     lib.pic_read_fields.restype = ctypes.c_int
     lib.pic_read_fields.argtypes = [vp, ctypes.c_int, _dp]
     lib.pic_read_particles.restype = ctypes.c_int
@@ -277,13 +277,41 @@ class Simulation:
         self._check(self._lib.pic_timing(self._h, _p(ms), cnt, int(bool(reset))))
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_FAMILIES)}
 
-    def grad(self, omega0, nsteps):
+    def grad(self, omega0, nsteps, ckpt_every=0):
+        """pic_grad: advance nsteps and return (L, dL/dwp, dL/dgamma), maps (nx, ny, nz)."""
         N = self.n[0] * self.n[1] * self.n[2]
         L = np.zeros(1)
         gw = np.zeros(N)
         gg = np.zeros(N)
-        self._check(self._lib.pic_grad(self._h, float(omega0), int(nsteps), _p(L), _p(gw), _p(gg)))
-        return L[0], from_compact(gw, self.n), from_compact(gg, self.n)
+        self._check(self._lib.pic_grad(self._h, float(omega0), int(nsteps), int(ckpt_every), _p(L),
+                                       _p(gw), _p(gg)))
+        return float(L[0]), from_compact(gw, self.n), from_compact(gg, self.n)
+
+
+def spp_power(make_sim, omega0, nsteps, ckpt_every=0):
+    """A torch.autograd.Function-backed map (wp_map, gamma_map) -> L.
+
+    ``make_sim(wp, gamma)`` builds a fresh Simulation from numpy maps (nx, ny,
+    nz).  Calling the returned function with two float64 tensors runs pic_grad
+    once: its forward pass yields L and the adjoint's gradients, which the
+    backward pass scales by the incoming gradient.
+    """
+    import torch
+
+    class SppPower(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, wp, gamma):
+            sim = make_sim(wp.detach().cpu().double().numpy(), gamma.detach().cpu().double().numpy())
+            L, gw, gg = sim.grad(omega0, nsteps, ckpt_every)
+            ctx.save_for_backward(torch.from_numpy(gw).to(wp.device), torch.from_numpy(gg).to(gamma.device))
+            return torch.tensor(L, dtype=torch.float64, device=wp.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            gw, gg = ctx.saved_tensors
+            return g * gw, g * gg
+
+    return SppPower.apply
 
 
 def from_workload(w, with_bunch=True, **kw):

@@ -1,0 +1,240 @@
+"""pic_grad on the GPU (FP32 adjoint, FP64 accumulation) against the oracle.
+
+The oracle's adjoint gradient is itself pinned to FP64 central differences
+(test_oracle_adjoint); here the GPU gradient is compared with it and, on a
+few cells, with the oracle's central differences directly.  Tolerances are
+the forward parity bars: 1e-5 relative (L, and L2 over the gradient maps)
+for fields-only runs, FP32 forward and adjoint against FP64; 1e-3 with a
+bunch, whose FP32 recorded current differs from the oracle's FP64 one by the
+particle tolerance.
+"""
+import numpy as np
+import pytest
+
+import pic_inputs as pi
+from oracle import pic_oracle as po
+from paper_1505_04007_amd import native
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _workload(bc, npml, with_bunch, seed=0):
+    nx, ny, nz, dx = 40, 12, 28, 2e-9
+    k0, k1 = 10, 14
+    wp, g = pi.film_maps(nx, ny, nz, k0, k1)
+    rng = np.random.default_rng(pi.SEED0 + 720 + seed)
+    metal = wp > 0
+    wp[metal] *= 1.0 + 0.05 * rng.standard_normal(int(metal.sum()))
+    g[metal] *= 1.0 + 0.05 * rng.standard_normal(int(metal.sum()))
+    bunch = None
+    if with_bunch:
+        bunch = pi.gaussian_bunch(rng, 400, ((npml + 6) * dx, ny / 2 * dx, (k1 + 3) * dx),
+                                  (2 * dx, 1.5 * dx, 1.5 * dx), 50e3, charge=1e-16)
+    probes = np.array([[20 * dx, 6 * dx, (k1 + 1.4) * dx], [27 * dx, 5 * dx, (k1 + 0.6) * dx]])
+    return pi.Workload("grad_40x12x28", nx, ny, nz, dx, pi.courant_dt(dx), bc, npml, wp, g, bunch,
+                       probes, np.array([0.68 * pi.AG_WP]), 150, sort_every=10 if with_bunch else 0)
+
+
+def _pulse(w):
+    n = (w.nx, w.ny, w.nz)
+    p = pi.GaussianPulse(np.array(n) * w.dx * np.array([0.45, 0.5, 0.65]), 2.0 * w.dx,
+                         [2e6, -1e6, 3e6])
+    E = pi.sample_field(p, "E", n, w.dx)
+    # admissible initial field: periodic copies, zero tangential E on walls
+    for c in range(3):
+        for a in range(3):
+            if a == c:
+                continue
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[a], hi[a] = 0, n[a]
+            if w.bc[a] == native.BC_PERIODIC:
+                E[c][tuple(hi)] = E[c][tuple(lo)]
+            else:
+                E[c][tuple(lo)] = 0.0
+                E[c][tuple(hi)] = 0.0
+    return E
+
+
+def _oracle(w, E, wp=None, g=None, bunch=True):
+    o = po.OracleSim(w.nx, w.ny, w.nz, w.dx, w.dt, bc=w.bc, npml=w.npml, pml=w.pml,
+                     wp_map=w.wp_map if wp is None else wp, gamma_map=w.gamma_map if g is None else g)
+    for c in range(3):
+        o.E[c][...] = E[c]
+    if bunch and w.bunch is not None:
+        b = w.bunch
+        o.set_particles(b.x, b.y, b.z, b.ux, b.uy, b.uz, b.q, b.m, b.w)
+    o.set_probes(w.probes, w.omega)
+    return o
+
+
+def _gpu(w, E, **kw):
+    n = (w.nx, w.ny, w.nz)
+    return native.from_workload(w, init_E=[E[c][: n[0], : n[1], : n[2]] for c in range(3)], **kw)
+
+
+BCS = [
+    ((native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4),
+    ((native.BC_CPML,) * 3, 3),
+    ((native.BC_PERIODIC, native.BC_PEC, native.BC_PEC), 0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(BCS)))
+def test_fields_only_gradient_matches_oracle_adjoint(case):
+    bc, npml = BCS[case]
+    w = _workload(bc, npml, False, seed=case)
+    E = _pulse(w)
+    N, w0 = 150, w.omega[0]
+    o = _oracle(w, E)
+    Lo, gwo, ggo = o.grad(N, w0)
+    s = _gpu(w, E)
+    L, gw, gg = s.grad(w0, N)
+    print(f"case {case}: L rel {abs(L - Lo) / Lo:.2e}  dwp rel {_rel(gw, gwo):.2e}  "
+          f"dgamma rel {_rel(gg, ggo):.2e}", flush=True)
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert _rel(gw, gwo) <= 1e-5
+    assert _rel(gg, ggo) <= 1e-5
+    assert np.all(gw[w.wp_map == 0] == 0) and np.all(gg[w.wp_map == 0] == 0)
+
+
+def test_gradient_with_bunch_matches_oracle_adjoint():
+    w = _workload((native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, True)
+    E = _pulse(w)
+    for c in range(3):
+        E[c] *= 0.0  # the bunch alone drives the film
+    N, w0 = 120, w.omega[0]
+    o = _oracle(w, E)
+    Lo, gwo, ggo = o.grad(N, w0)
+    s = _gpu(w, E)
+    L, gw, gg = s.grad(w0, N)
+    print(f"bunch: L rel {abs(L - Lo) / Lo:.2e}  dwp rel {_rel(gw, gwo):.2e}  "
+          f"dgamma rel {_rel(gg, ggo):.2e}", flush=True)
+    assert Lo > 0
+    assert abs(L - Lo) <= 1e-3 * Lo
+    assert _rel(gw, gwo) <= 1e-3
+    assert _rel(gg, ggo) <= 1e-3
+    assert s.stats()["steps"] == N
+
+
+def test_gradient_matches_oracle_central_differences():
+    w = _workload((native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, False, seed=5)
+    E = _pulse(w)
+    N, w0 = 120, w.omega[0]
+    s = _gpu(w, E)
+    _, gw, gg = s.grad(w0, N)
+
+    def L_of(wp, g):
+        o = _oracle(w, E, wp, g)
+        o.step(N)
+        return float(np.sum(np.abs(o.probe()) ** 2))
+
+    rng = np.random.default_rng(pi.SEED0 + 730)
+    cells = np.argwhere(w.wp_map > 0)
+    # cells where the gradient is large enough to be resolved by FP32
+    big = [c for c in cells if abs(gw[tuple(c)]) > 1e-2 * np.abs(gw).max()]
+    pick = [big[q] for q in rng.choice(len(big), 6, replace=False)]
+    for (i, j, k) in pick:
+        for name, base, grad, h in (("wp", w.wp_map, gw, 1e-4), ("gamma", w.gamma_map, gg, 1e-2)):
+            d = h * base[i, j, k]
+            up, dn = base.copy(), base.copy()
+            up[i, j, k] += d
+            dn[i, j, k] -= d
+            if name == "wp":
+                fd = (L_of(up, w.gamma_map) - L_of(dn, w.gamma_map)) / (2 * d)
+            else:
+                fd = (L_of(w.wp_map, up) - L_of(w.wp_map, dn)) / (2 * d)
+            scale = np.abs(grad).max()
+            assert abs(grad[i, j, k] - fd) <= 1e-2 * abs(fd) + 1e-4 * scale, (name, (i, j, k), grad[i, j, k], fd)
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    """Fields-only replays are deterministic, so every interval gives the same bits."""
+    w = _workload((native.BC_CPML, native.BC_CPML, native.BC_PERIODIC), 3, False, seed=2)
+    E = _pulse(w)
+    N, w0 = 61, w.omega[0]
+    ref = None
+    for ck in (0, 1, 7, 61, 100):
+        s = _gpu(w, E)
+        out = s.grad(w0, N, ckpt_every=ck)
+        if ref is None:
+            ref = out
+        else:
+            assert out[0] == ref[0]
+            assert np.array_equal(out[1], ref[1]) and np.array_equal(out[2], ref[2]), ck
+
+
+def test_grad_leaves_the_state_of_a_plain_run():
+    """After pic_grad(N) the simulation equals one stepped N times (fields-only: bitwise)."""
+    w = _workload((native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, False, seed=3)
+    E = _pulse(w)
+    a = _gpu(w, E)
+    b = _gpu(w, E)
+    a.step(7)
+    b.step(7)
+    a.grad(w.omega[0], 40, ckpt_every=6)
+    b.step(40)
+    for which in (native.FIELD_E, native.FIELD_H, native.FIELD_JPOL):
+        assert np.array_equal(a.fields(which), b.fields(which))
+    assert np.array_equal(a.probe(), b.probe())
+    assert a.stats()["steps"] == b.stats()["steps"] == 47
+    # and it keeps stepping identically afterwards
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(a.fields(native.FIELD_E), b.fields(native.FIELD_E))
+
+
+def test_grad_from_a_later_start_uses_absolute_step_phases():
+    """F sums from the step after the current one; the oracle's grad does the same."""
+    w = _workload((native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, False, seed=4)
+    E = _pulse(w)
+    o = _oracle(w, E)
+    o.step(9)
+    Lo, gwo, _ = o.grad(50, w.omega[0])
+    s = _gpu(w, E)
+    s.step(9)
+    L, gw, _ = s.grad(w.omega[0], 50)
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert _rel(gw, gwo) <= 1e-5
+
+
+def test_grad_rejects_bad_arguments_and_handles_no_signal():
+    w = _workload((native.BC_PEC,) * 3, 0, False)
+    s = native.Simulation(w.nx, w.ny, w.nz, w.dx, w.dt, w.wp_map, w.gamma_map)  # no probes
+    with pytest.raises(native.PicError) as ei:
+        s.grad(1e16, 10)
+    assert ei.value.status == native.PIC_EINVAL
+    s2 = native.from_workload(w)
+    for bad in ((1e16, 0, 0), (1e16, 5, -1), (float("nan"), 5, 0)):
+        with pytest.raises(native.PicError) as ei:
+            s2.grad(*bad)
+        assert ei.value.status == native.PIC_EINVAL
+    L, gw, gg = s2.grad(1e16, 20)  # zero field, no bunch
+    assert L == 0.0 and not gw.any() and not gg.any()
+
+
+def test_spp_power_autograd_function():
+    import torch
+    w = _workload((native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, False, seed=6)
+    E = _pulse(w)
+    N, w0 = 60, w.omega[0]
+
+    def make(wp, g):
+        return native.Simulation(w.nx, w.ny, w.nz, w.dx, w.dt, wp, g, bc=w.bc, npml=w.npml, pml=w.pml,
+                                 probes=w.probes, omega=w.omega,
+                                 init_E=[E[c][: w.nx, : w.ny, : w.nz] for c in range(3)])
+
+    f = native.spp_power(make, w0, N)
+    wp = torch.tensor(w.wp_map, dtype=torch.float64, requires_grad=True)
+    g = torch.tensor(w.gamma_map, dtype=torch.float64, requires_grad=True)
+    L = f(wp, g)
+    (3.0 * L).backward()
+    L2, gw, gg = make(w.wp_map, w.gamma_map).grad(w0, N)
+    assert float(L.detach()) == L2
+    assert np.array_equal(wp.grad.numpy(), 3.0 * gw)
+    assert np.array_equal(g.grad.numpy(), 3.0 * gg)

@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -191,10 +193,59 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """pic_grad on the 128x64x64, 20 nm film, 1e5-particle workload: the
+    differentiated run (forward with checkpoints + recorded bunch current,
+    replay, adjoint) against the plain forward run of the same steps."""
+    import torch
+    import pic_inputs as pi
+    from paper_1505_04007_amd import native
+
+    w = pi.film_adjoint()
+    N = args.steps if args.steps is not None else w.steps
+    w0 = w.meta["omega0"]
+    warm = native.from_workload(w)
+    warm.grad(w0, max(args.warmup, 1))
+    warm.close()
+    plain = native.from_workload(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.step(N)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    pushes = plain.stats()["pushes"]
+    plain.close()
+    print(f"[bench] plain {N} steps: {tf:.3f} s", file=sys.stderr, flush=True)
+    sim = native.from_workload(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, gw, gg = sim.grad(w0, N)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    print(f"[bench] pic_grad {N} steps: {tg:.3f} s, L = {L:.4e}", file=sys.stderr, flush=True)
+    gcells = w.cells * N / tg / 1e9
+    out = {"metric": METRIC, "value": round(gcells, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
+           "steps": N, "warmup": args.warmup, "ms_per_step": round(1e3 * tg / N, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": w.name + "_adjoint", "cells": w.cells, "particles": w.bunch.n,
+                      "sort_every": w.sort_every, "objective": "sum_p |F_p(0.68 wp)|^2",
+                      "ckpt_every": int(np.ceil(np.sqrt(N))), "parallelism": "single-gpu"},
+           "plain_forward": {"value": round(w.cells * N / tf / 1e9, 3), "unit": "Gcell-updates/s",
+                             "seconds": round(tf, 4), "particle_pushes_per_s": round(pushes / tf, 1)},
+           "grad_seconds": round(tg, 4),
+           "adjoint_vs_plain": round(tg / tf, 3),
+           "grad_norms": {"dL_dwp": float(np.linalg.norm(gw)), "dL_dgamma": float(np.linalg.norm(gg)),
+                          "L": L},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 200; the adjoint workload: its 2000)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="grating40nm_512x256x256_cpml12")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -225,8 +276,14 @@ def main():
 
     if args.workload == "batched16":
         torch.cuda.set_device(0)
+        args.steps = 200 if args.steps is None else args.steps
         bench_batched(args)
         return
+    if args.workload == "adjoint":
+        torch.cuda.set_device(0)
+        bench_adjoint(args)
+        return
+    args.steps = 200 if args.steps is None else args.steps
     w = workload(args.workload)
     torch.cuda.set_device(0)
     sim = native.from_workload(w, timing=True, deposit_mode=args.deposit_mode)

@@ -232,6 +232,60 @@ def batched_sweep(nparticles=200_000):
     return out
 
 
+# Drude constants of the paper's own workload (Sec. III), eps_inf = 1.
+PAPER_WP = 1.2e16
+PAPER_GAMMA = 1.45e13
+
+
+def paper_film(d_nm, dx=2e-9, t_fs=40.0, gap_nm=10.0, kinetic_ev=100e3, nparticles=4000,
+               npml=10, current_density=1e9, below_nm=100.0, above_nm=100.0, probe_um=1.5):
+    """The paper's geometry (Sec. III): film normal along x, bunch along +z,
+    periodic y, Ez probe on the film surface 1.5 um downstream of the bunch start.
+
+    x: CPML | 100 nm vacuum | film d | 100 nm vacuum | CPML (the surface modes
+    decay over ~30 nm into vacuum; with 30-50 nm gaps the layers pulled the
+    thin-film lower branch by ~100 THz).  y: 4 periodic cells,
+    the bunch uniform across them (a sheet beam: the modes it drives have no y
+    wavenumber, as in the dispersion relation of Table 1).  z: long enough that
+    the bunch stays clear of the far layer for t_fs.  Bunch: Gaussian in x
+    (sigma 2 nm, centre gap_nm above the film) and z (sigma 5 nm), 3-sigma
+    truncated, cold, along +z, with the peak current density of Sec. III
+    (100 kA/cm^2 = 1e9 A/m^2): Q = J ly 2 pi sx sz / v.  At that density the
+    bunch's space charge is negligible and it moves on straight lines.
+    """
+    rng = np.random.default_rng(SEED0 + 5)
+    i0 = npml + int(round(below_nm * 1e-9 / dx))
+    i1 = i0 + int(round(d_nm * 1e-9 / dx))
+    nx = i1 + int(round(above_nm * 1e-9 / dx)) + npml
+    ny = 4
+    dt = courant_dt(dx)
+    g = 1.0 + kinetic_ev / MEC2_EV
+    v = C_LIGHT * np.sqrt(1.0 - 1.0 / (g * g))
+    steps = int(np.ceil(t_fs * 1e-15 / dt))
+    z0 = (npml + 12) * dx + 15e-9
+    zp = z0 + probe_um * 1e-6
+    z_end = z0 + v * steps * dt + 80e-9
+    nz = int(np.ceil(max(z_end, zp + 200e-9) / dx)) + npml
+    wpm = np.zeros((nx, ny, nz))
+    gm = np.zeros((nx, ny, nz))
+    wpm[i0:i1] = PAPER_WP
+    gm[i0:i1] = PAPER_GAMMA
+    top = i1 * dx
+    xs = top + gap_nm * 1e-9 + 2e-9 * truncated_normal(rng, nparticles)
+    ys = rng.uniform(0.0, ny * dx, nparticles)
+    zs = z0 + 5e-9 * truncated_normal(rng, nparticles)
+    u = beam_u(kinetic_ev)
+    charge = current_density * ny * dx * 2 * np.pi * 2e-9 * 5e-9 / v
+    bunch = Bunch(xs, ys, zs, np.zeros(nparticles), np.zeros(nparticles), np.full(nparticles, u),
+                  -E_CHARGE, M_E, charge / (nparticles * E_CHARGE))
+    probes = np.array([[top + 1e-9, ny * dx / 2, zp]])
+    omega = 2 * np.pi * 1e12 * np.arange(500.0, 1800.0, 1.0)  # 1 THz grid
+    return Workload(f"paperfilm{d_nm}nm_{nx}x{ny}x{nz}", nx, ny, nz, dx, dt, (CPML, PERIODIC, CPML),
+                    npml, wpm, gm, bunch, probes, omega, steps,
+                    sort_every=20,
+                    meta={"thickness_nm": d_nm, "z0": z0, "z_probe": zp, "v": v, "film_top": top})
+
+
 # ---------------------------------------------------------------------------
 # Smooth initial fields (sampled by each side at its own Yee positions)
 # ---------------------------------------------------------------------------

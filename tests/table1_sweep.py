@@ -1,0 +1,88 @@
+"""Physics validation in the paper's geometry (Sec. III-IV, Table 1).
+
+A 100 keV sheet bunch glides over a Drude film (wp = 1.2e16 rad/s,
+gamma = 1.45e13 1/s) with the film normal along x and the bunch along z;
+Ez is sampled on the film surface 1.5 um downstream.  The probe spectrum
+peaks where the film's two surface-mode branches cross the electron line
+w = beta c k: the "theoretical value" columns of Table 1, computed here by
+tests/dispersion.py.  The spectrum is the library's own FP64 probe DFT
+(F(w) = sum_n dt Ez^n exp(-i w n dt) over the whole run, on a 1 THz grid);
+its two strongest local maxima are the measured branches.  Their frequency
+resolution is about 1/T (25 THz for 40 fs), so films of 60 nm and more, whose
+branches lie closer than that, show one merged peak.
+
+Run as a script (GPU) for the whole table:  python tests/table1_sweep.py [dx_nm]
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+sys.path.insert(0, HERE)
+
+import pic_inputs as pi  # noqa: E402
+from dispersion import beta_of, film_modes_on_line  # noqa: E402
+
+THICKNESSES = (20, 30, 40, 50, 60, 70, 80, 150)
+
+
+def theory_thz(d_nm, kinetic_ev=100e3):
+    lo, hi = film_modes_on_line(pi.PAPER_WP, d_nm * 1e-9, beta_of(kinetic_ev))
+    return lo / (2 * np.pi * 1e12), hi / (2 * np.pi * 1e12)
+
+
+def golden_pic():
+    out = {}
+    for line in open(os.path.join(HERE, "golden", "table1_pic.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        d, lo, hi = line.split()
+        out[int(d)] = (float(lo), float(hi))
+    return out
+
+
+def two_peaks(f, a):
+    """Frequencies of the two largest local maxima of a(f), ascending."""
+    i = np.where((a[1:-1] > a[:-2]) & (a[1:-1] >= a[2:]))[0] + 1
+    if i.size == 0:
+        return np.nan, np.nan
+    top = i[np.argsort(a[i])[::-1][:2]]
+    fs = np.sort(f[top])
+    if fs.size == 1:
+        return fs[0], np.nan
+    return fs[0], fs[1]
+
+
+def run_film(d_nm, dx=2e-9, t_fs=40.0):
+    """Simulate one film on the GPU; returns the measured branches (THz)."""
+    from paper_1505_04007_amd import native
+    w = pi.paper_film(d_nm, dx=dx, t_fs=t_fs)
+    sim = native.from_workload(w)
+    sim.step(w.steps)
+    F = sim.probe()[0]
+    f = w.omega / (2 * np.pi * 1e12)
+    lo, hi = two_peaks(f, np.abs(F))
+    st = sim.stats()
+    sim.close()
+    return {"d_nm": d_nm, "lower": lo, "upper": hi, "cells": w.cells, "steps": w.steps,
+            "live": st["live"], "record_fs": w.steps * w.dt * 1e15}
+
+
+def main(argv):
+    dx = float(argv[1]) * 1e-9 if len(argv) > 1 else 2e-9
+    gp = golden_pic()
+    print(f"dx = {dx * 1e9:.1f} nm; frequencies in THz")
+    print(f"{'d_nm':>5} | {'theory lo':>9} {'hi':>7} | {'here lo':>8} {'hi':>7} | "
+          f"{'paper PIC lo':>12} {'hi':>7}")
+    for d in THICKNESSES:
+        th = theory_thz(d)
+        r = run_film(d, dx=dx)
+        p = gp.get(d, (np.nan, np.nan))
+        print(f"{d:5d} | {th[0]:9.1f} {th[1]:7.1f} | {r['lower']:8.1f} {r['upper']:7.1f} | "
+              f"{p[0]:12.1f} {p[1]:7.1f}", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv)

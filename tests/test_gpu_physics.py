@@ -3,9 +3,12 @@
 Thin films, where the two branches are well separated: the probe spectrum's
 two peaks must sit at the dispersion-relation crossings within the spectral
 resolution of the record, 1/T = 25 THz for 40 fs (the first-order staircase
-error of the film surfaces at 2 nm cells is below that: ~0.5-1 %).  The
-paper's own PIC column is printed beside them; it is not a pin (the paper's
-bunch and domain are not fully specified).
+error of the film surfaces at 2 nm cells is below that for thin films).  A
+thick film (one merged branch, the single-interface limit) shows the
+staircase error plainly: its peak lies below the crossing by ~3 % at 2 nm
+cells and half that at 1 nm, and the Richardson value meets the crossing.
+The paper's own PIC column is printed beside them; it is not a pin (the
+paper's bunch and domain are not fully specified).
 """
 import numpy as np
 import pytest
@@ -26,3 +29,15 @@ def test_thin_film_branches_match_dispersion_crossings(d_nm):
     res = 1e3 / r["record_fs"]  # THz
     assert abs(r["lower"] - lo) <= res
     assert abs(r["upper"] - hi) <= res
+
+
+def test_thick_film_converges_first_order_to_the_crossing():
+    d = 150
+    th = ts.theory_thz(d)[0]
+    f2 = ts.run_film(d, dx=2e-9)["lower"]
+    f1 = ts.run_film(d, dx=1e-9)["lower"]
+    ex = 2 * f1 - f2
+    print(f"d = {d} nm: 2 nm {f2:.0f}, 1 nm {f1:.0f}, extrapolated {ex:.0f}, theory {th:.0f} THz", flush=True)
+    assert f2 < f1 < th + 25.0  # approached from below, error shrinking with the cell
+    assert abs(th - f1) < 0.75 * abs(th - f2)
+    assert abs(ex - th) <= 25.0

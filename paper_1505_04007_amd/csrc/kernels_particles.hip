@@ -215,7 +215,7 @@ __device__ __forceinline__ void make_dep(const float S0[3][3], const float dS[3]
         }
 }
 
-// Current of slot s scaled by f (f = 0 silences a lane).
+// Current of slot s, scaled by f.
 __device__ __forceinline__ float slot_value(const Dep &d, int s, float f)
 {
     int comp, oi, oj, ok;
@@ -275,13 +275,16 @@ __device__ __forceinline__ void halve_dpp(float *v, int lane)
 
 // Rounds of width 32 and 16: the lower half-wave keeps slot e, the upper
 // keeps slot e + OFF; a half-wave swap of the two registers puts each half's
-// partner values next to its own, and the sum finishes the round.
-__device__ __forceinline__ void halve32(float *v)
+// partner values next to its own, and the sum finishes the round.  The first
+// round reads the 54 slot currents of a lane, or zeros for a lane outside
+// the round's window.
+__device__ __forceinline__ void halve32(const float *val, bool mine, float *v)
 {
 #pragma unroll
     for (int e = 0; e < 32; ++e) {
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[e]), __float_as_uint(v[e + 32]),
-                                                        false, false);
+        const float lo = mine ? val[e] : 0.f;
+        const float hi = (e + 32 < 54 && mine) ? val[e + 32 < 54 ? e + 32 : 0] : 0.f;
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
         v[e] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 }
@@ -296,10 +299,12 @@ __device__ __forceinline__ void halve16(float *v)
     }
 }
 
-// After the six rounds lane l holds the wavefront sum of slot l.
-__device__ __forceinline__ float wave_reduce64(float *v, int lane)
+// After the six rounds lane l holds the sum of slot l over the lanes with
+// `mine` set.
+__device__ __forceinline__ float wave_reduce64(const float *val, bool mine, int lane)
 {
-    halve32(v);
+    float v[32];
+    halve32(val, mine, v);
     halve16(v);
     halve_dpp<8>(v, lane);
     halve_dpp<4>(v, lane);
@@ -308,7 +313,9 @@ __device__ __forceinline__ float wave_reduce64(float *v, int lane)
     return v[0];
 }
 
-constexpr int MAX_ROUNDS = 4;
+// Windows summed by wavefront rounds before the remaining lanes switch to
+// per-lane atomics (a round costs about one per-lane slot loop / 4).
+constexpr int MAX_ROUNDS = 16;
 
 template <int MODE, int PX>
 __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
@@ -400,52 +407,47 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
             }
         }
     }
+    // the 54 slot currents of this particle's move (0 for a lane that does not deposit)
     const float qd = a.qd;
+    float val[54];
+#pragma unroll
+    for (int s = 0; s < 54; ++s) val[s] = slot_value(d, s, qd);
     const unsigned long long live = __ballot(dep);
     // per-wavefront push counter (one slot per wavefront of the launch)
     if (lane == 0 && live) a.pushes[p >> 6] += (unsigned long long)__popcll(live);
-    if (MODE == 1) {
-        if (dep) {
-#pragma unroll
-            for (int s = 0; s < 54; ++s) {
-                const float v = slot_value(d, s, qd);
-                if (v != 0.f) {
-                    float *ad = slot_addr(a, s, base[0], base[1], base[2]);
-                    if (ad) atomicAdd(ad, v);
-                }
-            }
-        }
-        return;
-    }
-    const int key = (base[0] + 1) + (a.nx + 2) * ((base[1] + 1) + (a.ny + 2) * (base[2] + 1));
     unsigned long long rem = live;
-    int round = 0;
-    while (rem && round < MAX_ROUNDS) {
-        const int leader = __ffsll((long long)rem) - 1;
-        const int k0 = __builtin_amdgcn_readlane(key, leader);
-        const bool mine = ((rem >> lane) & 1ull) && key == k0;
-        const unsigned long long m = __ballot(mine);
-        const float f = mine ? 1.f : 0.f;
-        float v[64];
-#pragma unroll
-        for (int s = 0; s < 54; ++s) v[s] = slot_value(d, s, f);
-#pragma unroll
-        for (int s = 54; s < 64; ++s) v[s] = 0.f;
-        const float tot = wave_reduce64(v, lane);
-        const int bx = __builtin_amdgcn_readlane(base[0], leader);
-        const int by = __builtin_amdgcn_readlane(base[1], leader);
-        const int bz = __builtin_amdgcn_readlane(base[2], leader);
-        if (lane < 54 && tot != 0.f) {
-            float *ad = slot_addr(a, lane, bx, by, bz);
-            if (ad) atomicAdd(ad, qd * tot);
+    if (MODE != 1) {
+        // lane l < 54 owns slot l of every round's window: its component and
+        // offset from the window's base node, computed once
+        int lc, li, lj, lk;
+        slot_geom(lane < 54 ? lane : 0, lc, li, lj, lk);
+        const int lrel = li + a.nx * (lj + a.ny * lk);
+        float *Jl = lc == 0 ? a.Jb[0] : (lc == 1 ? a.Jb[1] : a.Jb[2]);
+        const int key = (base[0] + 1) + (a.nx + 2) * ((base[1] + 1) + (a.ny + 2) * (base[2] + 1));
+        int round = 0;
+        while (rem && round < MAX_ROUNDS) {
+            const int leader = __ffsll((long long)rem) - 1;
+            const int k0 = __builtin_amdgcn_readlane(key, leader);
+            const bool mine = ((rem >> lane) & 1ull) && key == k0;
+            const unsigned long long m = __ballot(mine);
+            const float tot = wave_reduce64(val, mine, lane);
+            const int bx = __builtin_amdgcn_readlane(base[0], leader);
+            const int by = __builtin_amdgcn_readlane(base[1], leader);
+            const int bz = __builtin_amdgcn_readlane(base[2], leader);
+            if (lane < 54 && tot != 0.f) {
+                const bool inside = bx >= 0 && bx + 2 < a.nx && by >= 0 && by + 2 < a.ny && bz >= 0 &&
+                                    bz + 2 < a.nz;
+                float *ad = inside ? Jl + (bx + a.nx * (by + a.ny * bz)) + lrel : slot_addr(a, lane, bx, by, bz);
+                if (ad) atomicAdd(ad, tot);
+            }
+            rem &= ~m;
+            ++round;
         }
-        rem &= ~m;
-        ++round;
     }
     if ((rem >> lane) & 1ull) {
 #pragma unroll
         for (int s = 0; s < 54; ++s) {
-            const float v = slot_value(d, s, qd);
+            const float v = val[s];
             if (v != 0.f) {
                 float *ad = slot_addr(a, s, base[0], base[1], base[2]);
                 if (ad) atomicAdd(ad, v);

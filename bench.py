@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--workload", default="grating40nm_512x256x256_cpml12")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--deposit-mode", type=int, default=0)
+    ap.add_argument("--sort-every", type=int, default=None,
+                    help="override the workload's cell-sort interval")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -286,6 +288,8 @@ def main():
     args.steps = 200 if args.steps is None else args.steps
     w = workload(args.workload)
     torch.cuda.set_device(0)
+    if args.sort_every is not None:
+        w.sort_every = args.sort_every
     sim = native.from_workload(w, timing=True, deposit_mode=args.deposit_mode)
     print(f"[bench] {w.name}: {w.cells} cells, {w.bunch.n if w.bunch else 0} particles, "
           f"warmup {args.warmup}", file=sys.stderr, flush=True)

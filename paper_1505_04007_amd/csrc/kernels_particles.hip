@@ -186,7 +186,7 @@ __device__ __forceinline__ void slot_geom(int s, int &comp, int &oi, int &oj, in
 
 // Esirkepov factors of one move: the running sum of dS along each current's
 // own axis (pre[axis][edge]) and the transverse weight
-//   T = S0 S0 + (dS S0 + S0 dS)/2 + dS dS/3
+//   T = S0 S0' + (dS S0' + S0 dS')/2 + dS dS'/3 = A A' + dS dS'/12,  A = S0 + dS/2,
 // of the other two axes.  Slot s has current pre * T.  Every index used
 // below is a compile-time constant after unrolling, so nothing leaves
 // registers.
@@ -197,21 +197,24 @@ struct Dep {
 
 __device__ __forceinline__ void make_dep(const float S0[3][3], const float dS[3][3], Dep &d)
 {
+    float A[3][3], D[3][3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         d.pre[ax][0] = dS[ax][0];
         d.pre[ax][1] = dS[ax][0] + dS[ax][1];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            A[ax][m] = S0[ax][m] + 0.5f * dS[ax][m];
+            D[ax][m] = (1.f / 12.f) * dS[ax][m];
+        }
     }
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            d.Tyz[p][q] = S0[1][p] * S0[2][q] + 0.5f * (dS[1][p] * S0[2][q] + S0[1][p] * dS[2][q]) +
-                          (1.f / 3.f) * dS[1][p] * dS[2][q];
-            d.Txz[p][q] = S0[0][p] * S0[2][q] + 0.5f * (dS[0][p] * S0[2][q] + S0[0][p] * dS[2][q]) +
-                          (1.f / 3.f) * dS[0][p] * dS[2][q];
-            d.Txy[p][q] = S0[0][p] * S0[1][q] + 0.5f * (dS[0][p] * S0[1][q] + S0[0][p] * dS[1][q]) +
-                          (1.f / 3.f) * dS[0][p] * dS[1][q];
+            d.Tyz[p][q] = A[1][p] * A[2][q] + D[1][p] * dS[2][q];
+            d.Txz[p][q] = A[0][p] * A[2][q] + D[0][p] * dS[2][q];
+            d.Txy[p][q] = A[0][p] * A[1][q] + D[0][p] * dS[1][q];
         }
 }
 
@@ -519,30 +522,68 @@ void launch_fill_i32(int *p, int v, long long n, hipStream_t s)
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)nb), dim3(256), 0, s, p, v, n);
 }
 
+template <bool MAX>
+__device__ __forceinline__ int wave_minmax(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(v, off, 64);
+        v = MAX ? max(v, o) : min(v, o);
+    }
+    return v;
+}
+
+// Count particles per cell.  Lanes of a wavefront with the same cell (most
+// of them: the particles are nearly sorted from the last sort) reserve their
+// ranks with one atomic and take consecutive ones in lane order, so the
+// scatter writes them to consecutive places.
 __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
 {
     __shared__ int bb[6];
     if (threadIdx.x < 6) bb[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
     __syncthreads();
     const int p = blockIdx.x * PBLOCK + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int pc = a.st->pcur;
+    int key = a.ncell;
+    int cell[3] = {INT_MAX, INT_MAX, INT_MAX};
+    bool in = false;
     if (p < a.n) {
         const float x = a.P[pc][0][p], y = a.P[pc][1][p], z = a.P[pc][2][p];
-        int key = a.ncell;
         if (live_pos(x, y, z, a.nx, a.ny, a.nz)) {
-            const int i = min((int)x, a.nx - 1);
-            const int j = min((int)y, a.ny - 1);
-            const int k = min((int)z, a.nz - 1);
-            key = i + a.nx * (j + a.ny * k);
-            atomicMin(&bb[0], i);
-            atomicMin(&bb[1], j);
-            atomicMin(&bb[2], k);
-            atomicMax(&bb[3], i);
-            atomicMax(&bb[4], j);
-            atomicMax(&bb[5], k);
+            cell[0] = min((int)x, a.nx - 1);
+            cell[1] = min((int)y, a.ny - 1);
+            cell[2] = min((int)z, a.nz - 1);
+            key = cell[0] + a.nx * (cell[1] + a.ny * cell[2]);
+            in = true;
         }
+    }
+    unsigned long long rem = __ballot(p < a.n);
+    int rank = 0;
+    while (rem) {
+        const int leader = __ffsll((long long)rem) - 1;
+        const int k0 = __builtin_amdgcn_readlane(key, leader);
+        const unsigned long long m = __ballot(((rem >> lane) & 1ull) && key == k0);
+        int b = 0;
+        if (lane == leader) b = atomicAdd(&a.counts[k0], __popcll(m));
+        b = __builtin_amdgcn_readlane(b, leader);
+        if ((m >> lane) & 1ull) rank = b + __popcll(m & ((1ull << lane) - 1ull));
+        rem &= ~m;
+    }
+    if (p < a.n) {
         a.key[p] = key;
-        a.rank[p] = atomicAdd(&a.counts[key], 1);
+        a.rank[p] = rank;
+    }
+    // box of the live cells: wavefront min / max, then the workgroup's in LDS
+    const bool any = __ballot(in) != 0ull;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int lo = wave_minmax<false>(in ? cell[q] : INT_MAX);
+        const int hi = wave_minmax<true>(in ? cell[q] : INT_MIN);
+        if (lane == 0 && any) {
+            atomicMin(&bb[q], lo);
+            atomicMax(&bb[3 + q], hi);
+        }
     }
     __syncthreads();
     if (threadIdx.x < 3 && bb[threadIdx.x] != INT_MAX) atomicMin(&a.box[threadIdx.x], bb[threadIdx.x]);

@@ -149,6 +149,8 @@ def bench_batched(args):
     plain_s = 0.0
     for w in ws:
         sim = native.from_workload(w)
+        if not args.no_tune:
+            sim.tune(reps=5)
         sim.step(args.warmup)
         torch.cuda.synchronize()
         p0 = sim.stats()["pushes"]
@@ -162,6 +164,7 @@ def bench_batched(args):
     print(f"[bench] 16 plain runs: {plain_s:.3f} s", file=sys.stderr, flush=True)
     sims = [native.from_workload(w) for w in ws]
     batch = native.Batch(sims, use_graph=True)
+    tune = batch.tune(force=0) if args.no_tune else batch.tune(reps=5)
     batch.step(args.warmup)
     torch.cuda.synchronize()
     p0 = sum(s.stats()["pushes"] for s in sims)
@@ -181,7 +184,7 @@ def bench_batched(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batched16_film5-80nm_128x64x64-192x96x96", "instances": len(ws),
                       "cells": cells, "particles": sum(w.bunch.n for w in ws), "sort_every": 20,
-                      "parallelism": "single-gpu"},
+                      "field_tile": [tune["fx"], tune["fy"]], "parallelism": "single-gpu"},
            "particle_pushes_per_s": round(pushes / secs, 1),
            "plain_sequential": {"value": round(plain_g, 3), "unit": "Gcell-updates/s",
                                 "particle_pushes_per_s": round(pushes_total / plain_s, 1)},
@@ -252,6 +255,8 @@ def main():
     ap.add_argument("--deposit-mode", type=int, default=0)
     ap.add_argument("--sort-every", type=int, default=None,
                     help="override the workload's cell-sort interval")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default field tile instead of running the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -291,8 +296,9 @@ def main():
     if args.sort_every is not None:
         w.sort_every = args.sort_every
     sim = native.from_workload(w, timing=True, deposit_mode=args.deposit_mode)
+    tune = sim.tune(force=0) if args.no_tune else sim.tune(reps=10)
     print(f"[bench] {w.name}: {w.cells} cells, {w.bunch.n if w.bunch else 0} particles, "
-          f"warmup {args.warmup}", file=sys.stderr, flush=True)
+          f"warmup {args.warmup}, field tile {tune['fx']}x{tune['fy']}", file=sys.stderr, flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     p0 = sim.stats()["pushes"]
@@ -346,7 +352,8 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": w.name, "cells": w.cells,
                       "particles": w.bunch.n if w.bunch else 0, "sort_every": w.sort_every,
-                      "deposit_mode": args.deposit_mode, "parallelism": "single-gpu"},
+                      "deposit_mode": args.deposit_mode, "field_tile": [tune["fx"], tune["fy"]],
+                      "parallelism": "single-gpu"},
            "particle_pushes_per_s": round(pushes / secs, 1),
            "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 2
+#define PIC_ABI_VERSION 3
 
 typedef enum {
     PIC_OK = 0,
@@ -201,6 +201,28 @@ pic_status pic_probe(pic_ctx *ctx, double *re, double *im, double *series);
 pic_status pic_grad(pic_ctx *ctx, double omega0, int64_t nsteps, int64_t ckpt_every, double *L,
                     double *dL_dwp, double *dL_dgamma);
 
+/* Result of the field-kernel tile autotuner. */
+typedef struct {
+    int32_t tile;     /* chosen tile shape index */
+    int32_t fx, fy;   /* its cells along x and y (one z plane per workgroup) */
+    int32_t nshapes;  /* shapes in the table (entries of ms) */
+    double ms[8];     /* measured ms per H + E launch pair, per shape (0 when forced) */
+} pic_tune_out;
+
+/*
+ * Choose the tile shape of the field kernels (H update and Drude + E
+ * update) for this grid.  With force = -1, times reps H + E launch pairs of
+ * every shape in the library's table on the context's stream, starting from
+ * the current field state and restoring it afterwards (fields, CPML
+ * memories, Drude current, step clock), and keeps the fastest (the default
+ * shape 0 unless another is more than 3 % faster); with force in
+ * [0, nshapes) selects that shape without timing.  Results of later steps
+ * do not depend on the shape (each cell's arithmetic is the same).
+ * Synchronises the stream.  out may be NULL.  Errors: PIC_EINVAL, PIC_ENOMEM,
+ * PIC_EDEVICE.
+ */
+pic_status pic_tune(pic_ctx *ctx, int32_t reps, int32_t force, pic_tune_out *out);
+
 /* Copy one field (3 components, compact Yee layout, SI units) to host. */
 pic_status pic_read_fields(pic_ctx *ctx, int which, double *host_out);
 
@@ -248,6 +270,12 @@ void pic_destroy(pic_ctx *ctx);
 typedef struct pic_batch pic_batch;
 pic_status pic_batch_create(pic_batch **batch, pic_ctx *const *ctxs, int32_t n, int32_t use_graph);
 pic_status pic_batch_step(pic_batch *batch, int64_t nsteps);
+/*
+ * The autotuner for a batch: one tile shape for all members' field launches
+ * (the batched H and E kernels), timed like pic_tune over the whole batch
+ * with every member's state restored; re-captures the batch's graph.
+ */
+pic_status pic_batch_tune(pic_batch *b, int32_t reps, int32_t force, pic_tune_out *out);
 void pic_batch_destroy(pic_batch *batch);
 const char *pic_batch_last_error(const pic_batch *batch);
 

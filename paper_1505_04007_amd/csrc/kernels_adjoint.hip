@@ -29,7 +29,7 @@ __device__ __forceinline__ bool adj_tile_cell(const AdjArgs &a, int t, int &i, i
     k = t / (a.gx * a.gy);
     i = bx * FX + threadIdx.x;
     j = by * FY + threadIdx.y;
-    return i < a.nx && j < a.ny;
+    return i < a.nx && j < a.ny && k < a.nz;
 }
 
 template <int AX>

@@ -1,8 +1,9 @@
 // Yee curl updates for gfx950: H update (vacuum form) and the fused Drude
 // polarization-current + E update.
 //
-// One thread per cell, 64 x 4 threads per workgroup over an (x, y) tile of
-// one z plane; x is fastest so a wavefront reads one 256-byte row.  Each
+// One thread per cell, one workgroup per (x, y) tile of one z plane (64 x 4
+// cells by default; the autotuner picks another shape from a fixed table per
+// grid), x fastest so a wavefront reads contiguous rows.  Each
 // cell reads its own three old values and the three neighbour values its
 // curl needs (+x/+y/+z for H, -x/-y/-z for E); the neighbours are the own
 // values of adjacent lanes, rows and planes and are served by L1/L2, so the
@@ -220,27 +221,30 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
 
 // Decompose a tile index of one simulation into (i, j, k); false when the
 // thread lies past the grid's x / y extent.
+template <int TXW, int TYW>
 __device__ __forceinline__ bool tile_cell(const FieldArgs &a, int t, int &i, int &j, int &k)
 {
     const int bx = t % a.gx, by = (t / a.gx) % a.gy;
     k = t / (a.gx * a.gy);
-    i = bx * FX + threadIdx.x;
-    j = by * FY + threadIdx.y;
-    return i < a.nx && j < a.ny;
+    i = bx * TXW + threadIdx.x;
+    j = by * TYW + threadIdx.y;
+    return i < a.nx && j < a.ny && k < a.nz;
 }
 
-__global__ __launch_bounds__(FX *FY) void k_h_update(FieldArgs a)
+template <int TXW, int TYW>
+__global__ __launch_bounds__(TXW *TYW) void k_h_update(FieldArgs a)
 {
     int i, j, k;
-    if (!tile_cell(a, xcd_tile(), i, j, k)) return;
+    if (!tile_cell<TXW, TYW>(a, xcd_tile(), i, j, k)) return;
     const DevState s = *a.st;
     h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
 
-__global__ __launch_bounds__(FX *FY) void k_e_update(FieldArgs a)
+template <int TXW, int TYW>
+__global__ __launch_bounds__(TXW *TYW) void k_e_update(FieldArgs a)
 {
     int i, j, k;
-    if (!tile_cell(a, xcd_tile(), i, j, k)) return;
+    if (!tile_cell<TXW, TYW>(a, xcd_tile(), i, j, k)) return;
     const DevState s = *a.st;
     e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
@@ -253,46 +257,93 @@ __device__ __forceinline__ int owner(const int *start, int n, int t)
     return q;
 }
 
-__global__ __launch_bounds__(FX *FY) void k_h_update_batch(const FieldArgs *args, const int *start, int n)
+template <int TXW, int TYW>
+__global__ __launch_bounds__(TXW *TYW) void k_h_update_batch(const FieldArgs *args, const int *start, int n)
 {
     const int t = xcd_tile();
     const int q = owner(start, n, t);
     const FieldArgs &a = args[q];
     int i, j, k;
-    if (!tile_cell(a, t - start[q], i, j, k)) return;
+    if (!tile_cell<TXW, TYW>(a, t - start[q], i, j, k)) return;
     const DevState s = *a.st;
     h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
 
-__global__ __launch_bounds__(FX *FY) void k_e_update_batch(const FieldArgs *args, const int *start, int n)
+template <int TXW, int TYW>
+__global__ __launch_bounds__(TXW *TYW) void k_e_update_batch(const FieldArgs *args, const int *start, int n)
 {
     const int t = xcd_tile();
     const int q = owner(start, n, t);
     const FieldArgs &a = args[q];
     int i, j, k;
-    if (!tile_cell(a, t - start[q], i, j, k)) return;
+    if (!tile_cell<TXW, TYW>(a, t - start[q], i, j, k)) return;
     const DevState s = *a.st;
     e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
 
+// One launch of a tile-shape instantiation: the shape index selects the
+// template arguments (the table in pic_internal.hpp).
+template <template <int, int> class K, typename... Args>
+void launch_shape(int shape, int blocks, hipStream_t s, Args... args)
+{
+    switch (shape) {
+#define PIC_SHAPE(v)                                                                                          \
+    case v:                                                                                                   \
+        K<TILE_FX[v], TILE_FY[v]>::launch(blocks, s, args...);                                                \
+        break;
+        PIC_SHAPE(1) PIC_SHAPE(2) PIC_SHAPE(3) PIC_SHAPE(4) PIC_SHAPE(5) PIC_SHAPE(6) PIC_SHAPE(7)
+#undef PIC_SHAPE
+    default: K<TILE_FX[0], TILE_FY[0]>::launch(blocks, s, args...); break;
+    }
+}
+
+template <int TXW, int TYW>
+struct HLaunch {
+    static void launch(int blocks, hipStream_t s, FieldArgs a)
+    {
+        hipLaunchKernelGGL((k_h_update<TXW, TYW>), dim3(blocks), dim3(TXW, TYW), 0, s, a);
+    }
+};
+template <int TXW, int TYW>
+struct ELaunch {
+    static void launch(int blocks, hipStream_t s, FieldArgs a)
+    {
+        hipLaunchKernelGGL((k_e_update<TXW, TYW>), dim3(blocks), dim3(TXW, TYW), 0, s, a);
+    }
+};
+template <int TXW, int TYW>
+struct HBatchLaunch {
+    static void launch(int blocks, hipStream_t s, const FieldArgs *args, const int *start, int n)
+    {
+        hipLaunchKernelGGL((k_h_update_batch<TXW, TYW>), dim3(blocks), dim3(TXW, TYW), 0, s, args, start, n);
+    }
+};
+template <int TXW, int TYW>
+struct EBatchLaunch {
+    static void launch(int blocks, hipStream_t s, const FieldArgs *args, const int *start, int n)
+    {
+        hipLaunchKernelGGL((k_e_update_batch<TXW, TYW>), dim3(blocks), dim3(TXW, TYW), 0, s, args, start, n);
+    }
+};
+
 void launch_h_update(const FieldArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_h_update, dim3(field_tiles(a.nx, a.ny, a.nz)), dim3(FX, FY), 0, s, a);
+    launch_shape<HLaunch>(a.tile, field_tiles(a.nx, a.ny, a.nz, a.tile), s, a);
 }
 
 void launch_e_update(const FieldArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_e_update, dim3(field_tiles(a.nx, a.ny, a.nz)), dim3(FX, FY), 0, s, a);
+    launch_shape<ELaunch>(a.tile, field_tiles(a.nx, a.ny, a.nz, a.tile), s, a);
 }
 
-void launch_h_update_batch(const FieldArgs *args, const int *start, int n, int total, hipStream_t s)
+void launch_h_update_batch(const FieldArgs *args, const int *start, int n, int total, int shape, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_h_update_batch, dim3(total), dim3(FX, FY), 0, s, args, start, n);
+    launch_shape<HBatchLaunch>(shape, total, s, args, start, n);
 }
 
-void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int total, hipStream_t s)
+void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int total, int shape, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_e_update_batch, dim3(total), dim3(FX, FY), 0, s, args, start, n);
+    launch_shape<EBatchLaunch>(shape, total, s, args, start, n);
 }
 
 }  // namespace pic

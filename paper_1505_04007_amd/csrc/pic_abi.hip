@@ -86,6 +86,7 @@ struct pic_ctx {
     int *d_live = nullptr;
 
     long long step = 0;
+    int tile = 0;  // field-kernel tile shape (pic_tune)
     int sort_every = 0, check_every = 0;
     long long since_sort = 0;
 
@@ -176,8 +177,9 @@ void build_args(pic_ctx *c)
     a.nx = c->n[0];
     a.ny = c->n[1];
     a.nz = c->n[2];
-    a.gx = (c->n[0] + pic::FX - 1) / pic::FX;
-    a.gy = (c->n[1] + pic::FY - 1) / pic::FY;
+    a.tile = c->tile;
+    a.gx = (c->n[0] + pic::TILE_FX[c->tile] - 1) / pic::TILE_FX[c->tile];
+    a.gy = (c->n[1] + pic::TILE_FY[c->tile] - 1) / pic::TILE_FY[c->tile];
     a.S = (float)c->S;
     for (int d = 0; d < 3; ++d) {
         a.per[d] = c->per[d];
@@ -998,8 +1000,8 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double
     aa.nx = c->n[0];
     aa.ny = c->n[1];
     aa.nz = c->n[2];
-    aa.gx = c->fa.gx;
-    aa.gy = c->fa.gy;
+    aa.gx = (c->n[0] + pic::FX - 1) / pic::FX;  // the adjoint kernels use the default tile
+    aa.gy = (c->n[1] + pic::FY - 1) / pic::FY;
     aa.S = (float)c->S;
     for (int d = 0; d < 3; ++d) {
         aa.per[d] = c->per[d];
@@ -1130,6 +1132,67 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double
     return PIC_OK;
 }
 
+// The fastest shape; the default one unless another beats it by more than
+// 3 % (isolated H + E timings do not see the particle kernels' cache traffic
+// between them, so small margins do not carry over to whole steps).
+int pick_shape(const double *ms)
+{
+    int best = 0;
+    for (int v = 1; v < pic::N_TILE_SHAPES; ++v)
+        if (ms[v] < ms[best]) best = v;
+    return ms[best] < 0.97 * ms[0] ? best : 0;
+}
+
+// Average milliseconds of one H + E launch pair for every tile shape, timed
+// on the context's stream from its current field state; the state (fields,
+// CPML memories, Drude current, step clock, non-finite flag) is restored
+// afterwards.
+pic_status tune_fields(pic_ctx *c, int reps, double *ms)
+{
+    GradScratch g;
+    g.s = c->stream;
+    char *ck = nullptr;
+    TRY(galloc(c, g, &ck, state_bytes(c)));
+    Mirror m{};
+    TRY(ckpt_save(c, ck, m));
+    int nan0 = 0;
+    HIP_TRY(c, hipMemcpyAsync(&nan0, c->d_nan, 4, hipMemcpyDeviceToHost, c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0));
+    hipError_t er = hipEventCreate(&e1);
+    if (er != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, PIC_EDEVICE, "hipEventCreate failed: %s", hipGetErrorString(er));
+    }
+    pic_status st = PIC_OK;
+    for (int v = 0; v < pic::N_TILE_SHAPES && st == PIC_OK; ++v) {
+        pic::FieldArgs f = c->fa;
+        f.tile = v;
+        f.gx = (c->n[0] + pic::TILE_FX[v] - 1) / pic::TILE_FX[v];
+        f.gy = (c->n[1] + pic::TILE_FY[v] - 1) / pic::TILE_FY[v];
+        pic::launch_h_update(f, c->stream);
+        pic::launch_e_update(f, c->stream);
+        (void)hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps; ++r) {
+            pic::launch_h_update(f, c->stream);
+            pic::launch_e_update(f, c->stream);
+        }
+        (void)hipEventRecord(e1, c->stream);
+        hipError_t e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) st = fail(c, PIC_EDEVICE, "timing a tile shape failed: %s", hipGetErrorString(e));
+        ms[v] = (double)t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TRY(st);
+    TRY(ckpt_load(c, ck, m));
+    HIP_TRY(c, hipMemcpyAsync(c->d_nan, &nan0, 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1146,6 +1209,33 @@ pic_status pic_grad(pic_ctx *c, double omega0, int64_t nsteps, int64_t ckpt_ever
     long long K = ckpt_every > 0 ? (long long)ckpt_every : (long long)std::ceil(std::sqrt((double)nsteps));
     K = std::max(1LL, std::min<long long>(K, nsteps));
     return grad_impl(c, omega0, (long long)nsteps, K, L, dL_dwp, dL_dgamma);
+}
+
+// Field-kernel tile autotuner: time H + E launches of every tile shape on
+// the context's own grid, from a saved field state that is restored
+// afterwards, and keep the fastest.
+pic_status pic_tune(pic_ctx *c, int32_t reps, int32_t force, pic_tune_out *out)
+{
+    CHECK_CTX(c);
+    if (force < -1 || force >= pic::N_TILE_SHAPES)
+        return fail(c, PIC_EINVAL, "force must be -1 or a tile shape index below %d", pic::N_TILE_SHAPES);
+    if (force < 0 && reps < 1) return fail(c, PIC_EINVAL, "reps must be >= 1");
+    pic_tune_out res{};
+    res.nshapes = pic::N_TILE_SHAPES;
+    if (force >= 0) {
+        c->tile = force;
+    } else {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        pic_status st = tune_fields(c, reps, res.ms);
+        if (st != PIC_OK) return st;
+        c->tile = pick_shape(res.ms);
+    }
+    build_args(c);
+    res.tile = c->tile;
+    res.fx = pic::TILE_FX[c->tile];
+    res.fy = pic::TILE_FY[c->tile];
+    if (out) *out = res;
+    return PIC_OK;
 }
 
 pic_status pic_read_fields(pic_ctx *c, int which, double *out)
@@ -1316,6 +1406,7 @@ struct pic_batch {
     int total_tiles = 0, total_pblocks = 0;
     int push_mode = 0;  // bit 0: per-lane atomics, bit 1: some member has a periodic x axis
     int sort_every = 0;
+    int tile = 0;       // field-kernel tile shape shared by all members (pic_batch_tune)
     bool particles = false;
     bool use_graph = false;
     int graph_steps = 0;
@@ -1361,10 +1452,10 @@ void batch_free(pic_batch *b)
 void batch_launches(pic_batch *b)
 {
     const int n = (int)b->ctx.size();
-    pic::launch_h_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, b->stream);
+    pic::launch_h_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, b->tile, b->stream);
     if (b->particles)
         pic::launch_push_deposit_batch(b->d_pa, b->d_pblocks, n, b->total_pblocks, b->push_mode, b->stream);
-    pic::launch_e_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, b->stream);
+    pic::launch_e_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, b->tile, b->stream);
     pic::launch_probe_batch(b->d_pr, n, b->stream);
 }
 
@@ -1394,12 +1485,55 @@ pic_status batch_sorts(pic_batch *b, bool only_due)
 
 extern "C" {
 
+// Field argument blocks of every member for tile shape `shape`, and the
+// prefix table of tiles per member.
+pic_status batch_upload_fields(pic_batch *b, int shape)
+{
+    const int n = (int)b->ctx.size();
+    std::vector<pic::FieldArgs> fa(n);
+    std::vector<int> tiles(n + 1, 0);
+    for (int q = 0; q < n; ++q) {
+        const pic_ctx *c = b->ctx[q];
+        fa[q] = c->fa;
+        fa[q].tile = shape;
+        fa[q].gx = (c->n[0] + pic::TILE_FX[shape] - 1) / pic::TILE_FX[shape];
+        fa[q].gy = (c->n[1] + pic::TILE_FY[shape] - 1) / pic::TILE_FY[shape];
+        tiles[q + 1] = tiles[q] + pic::field_tiles(c->n[0], c->n[1], c->n[2], shape);
+    }
+    BHIP(b, hipMemcpy(b->d_fa, fa.data(), sizeof(pic::FieldArgs) * n, hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_tiles, tiles.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    b->tile = shape;
+    b->total_tiles = tiles[n];
+    return PIC_OK;
+}
+
+// Capture one sort period (sort_every steps, then the sorts; since_sort is 0
+// at the start of every replay); fields-only batches capture 10 steps.
+pic_status batch_capture(pic_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_steps = (b->particles && b->sort_every > 0) ? b->sort_every : 10;
+    BHIP(b, hipStreamSynchronize(b->ext));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    for (int s2 = 0; s2 < b->graph_steps; ++s2) batch_launches(b);
+    if (b->particles && b->sort_every > 0)
+        for (pic_ctx *c : b->ctx)
+            if (c->np > 0) pic::launch_sort(c->sa, c->scan_tmp, b->stream);
+    hipError_t e = hipStreamEndCapture(b->stream, &b->graph);  // always leave capture mode
+    if (e != hipSuccess) return bfail(b, PIC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return PIC_OK;
+}
+
 static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t n, int32_t use_graph)
 {
-    std::vector<pic::FieldArgs> fa(n);
     std::vector<pic::PartArgs> pa(n);
     std::vector<pic::ProbeArgs> pr(n);
-    std::vector<int> tiles(n + 1, 0), pblk(n + 1, 0);
+    std::vector<int> pblk(n + 1, 0);
     for (int q = 0; q < n; ++q) {
         pic_ctx *c = ctxs[q];
         if (!c || c->poisoned) return bfail(b, PIC_EINVAL, "context %d is NULL or poisoned", q);
@@ -1416,10 +1550,8 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
             if (c->per[0]) b->push_mode |= 2;
         }
         b->ctx.push_back(c);
-        fa[q] = c->fa;
         pa[q] = c->pa;
         pr[q] = c->pr;
-        tiles[q + 1] = tiles[q] + pic::field_tiles(c->n[0], c->n[1], c->n[2]);
         pblk[q + 1] = pblk[q] + (c->np + pic::PBLOCK - 1) / pic::PBLOCK;
     }
     b->ext = ctxs[0]->stream;
@@ -1427,33 +1559,19 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
     BHIP(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     BHIP(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     BHIP(b, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
-    b->total_tiles = tiles[n];
     b->total_pblocks = pblk[n];
     BHIP(b, hipMalloc(&b->d_fa, sizeof(pic::FieldArgs) * n));
     BHIP(b, hipMalloc(&b->d_pa, sizeof(pic::PartArgs) * n));
     BHIP(b, hipMalloc(&b->d_pr, sizeof(pic::ProbeArgs) * n));
     BHIP(b, hipMalloc(&b->d_tiles, sizeof(int) * (n + 1)));
     BHIP(b, hipMalloc(&b->d_pblocks, sizeof(int) * (n + 1)));
-    BHIP(b, hipMemcpy(b->d_fa, fa.data(), sizeof(pic::FieldArgs) * n, hipMemcpyHostToDevice));
+    pic_status st = batch_upload_fields(b, 0);
+    if (st != PIC_OK) return st;
     BHIP(b, hipMemcpy(b->d_pa, pa.data(), sizeof(pic::PartArgs) * n, hipMemcpyHostToDevice));
     BHIP(b, hipMemcpy(b->d_pr, pr.data(), sizeof(pic::ProbeArgs) * n, hipMemcpyHostToDevice));
-    BHIP(b, hipMemcpy(b->d_tiles, tiles.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
     BHIP(b, hipMemcpy(b->d_pblocks, pblk.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
     b->use_graph = use_graph != 0;
-    if (b->use_graph) {
-        // one sort period: sort_every steps, then the sorts (since_sort is 0 at
-        // the start of every replay); fields-only batches capture 10 steps
-        b->graph_steps = (b->particles && b->sort_every > 0) ? b->sort_every : 10;
-        BHIP(b, hipStreamSynchronize(b->ext));
-        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        for (int s2 = 0; s2 < b->graph_steps; ++s2) batch_launches(b);
-        if (b->particles && b->sort_every > 0)
-            for (pic_ctx *c : b->ctx)
-                if (c->np > 0) pic::launch_sort(c->sa, c->scan_tmp, b->stream);
-        hipError_t e = hipStreamEndCapture(b->stream, &b->graph);  // always leave capture mode
-        if (e != hipSuccess) return bfail(b, PIC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-        BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    }
+    if (b->use_graph) return batch_capture(b);
     return PIC_OK;
 }
 
@@ -1509,6 +1627,80 @@ pic_status pic_batch_step(pic_batch *b, int64_t nsteps)
     }
     BHIP(b, hipEventRecord(b->ev_out, b->stream));
     BHIP(b, hipStreamWaitEvent(b->ext, b->ev_out, 0));
+    return PIC_OK;
+}
+
+pic_status pic_batch_tune(pic_batch *b, int32_t reps, int32_t force, pic_tune_out *out)
+{
+    if (!b) return bfail(nullptr, PIC_EINVAL, "batch is NULL");
+    if (force < -1 || force >= pic::N_TILE_SHAPES)
+        return bfail(b, PIC_EINVAL, "force must be -1 or a tile shape index below %d", pic::N_TILE_SHAPES);
+    if (force < 0 && reps < 1) return bfail(b, PIC_EINVAL, "reps must be >= 1");
+    for (pic_ctx *c : b->ctx)
+        if (c->poisoned) return bfail(b, PIC_ESTATE, "a member context is poisoned");
+    pic_tune_out res{};
+    res.nshapes = pic::N_TILE_SHAPES;
+    int best = force;
+    if (force < 0) {
+        BHIP(b, hipStreamSynchronize(b->ext));
+        BHIP(b, hipStreamSynchronize(b->stream));
+        // save every member's field state; the timed launches advance it
+        std::vector<void *> saved;
+        std::vector<Mirror> mir(b->ctx.size());
+        pic_status st = PIC_OK;
+        for (size_t q = 0; q < b->ctx.size() && st == PIC_OK; ++q) {
+            void *p = nullptr;
+            if (hipMalloc(&p, state_bytes(b->ctx[q])) != hipSuccess) {
+                (void)hipGetLastError();
+                st = bfail(b, PIC_ENOMEM, "no device memory to save member %zu", q);
+                break;
+            }
+            saved.push_back(p);
+            if (ckpt_save(b->ctx[q], (char *)p, mir[q]) != PIC_OK) st = bfail(b, PIC_EDEVICE, "saving member %zu failed", q);
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (st == PIC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+            st = bfail(b, PIC_EDEVICE, "hipEventCreate failed");
+        if (st == PIC_OK && hipStreamSynchronize(b->ext) != hipSuccess) st = bfail(b, PIC_EDEVICE, "sync failed");
+        const int n = (int)b->ctx.size();
+        for (int v = 0; v < pic::N_TILE_SHAPES && st == PIC_OK; ++v) {
+            st = batch_upload_fields(b, v);
+            if (st != PIC_OK) break;
+            pic::launch_h_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, v, b->stream);
+            pic::launch_e_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, v, b->stream);
+            (void)hipEventRecord(e0, b->stream);
+            for (int r = 0; r < reps; ++r) {
+                pic::launch_h_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, v, b->stream);
+                pic::launch_e_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, v, b->stream);
+            }
+            (void)hipEventRecord(e1, b->stream);
+            float t = 0.f;
+            hipError_t e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) st = bfail(b, PIC_EDEVICE, "timing a tile shape failed: %s", hipGetErrorString(e));
+            res.ms[v] = (double)t / reps;
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (size_t q = 0; q < saved.size(); ++q) {
+            if (ckpt_load(b->ctx[q], (char *)saved[q], mir[q]) != PIC_OK && st == PIC_OK)
+                st = bfail(b, PIC_EDEVICE, "restoring member %zu failed", q);
+        }
+        (void)hipStreamSynchronize(b->ext);
+        for (void *p : saved) (void)hipFree(p);
+        if (st != PIC_OK) return st;
+        best = pick_shape(res.ms);
+    }
+    pic_status st = batch_upload_fields(b, best);
+    if (st != PIC_OK) return st;
+    if (b->use_graph) {
+        st = batch_capture(b);
+        if (st != PIC_OK) return st;
+    }
+    res.tile = best;
+    res.fx = pic::TILE_FX[best];
+    res.fy = pic::TILE_FY[best];
+    if (out) *out = res;
     return PIC_OK;
 }
 

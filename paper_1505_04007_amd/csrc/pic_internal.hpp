@@ -23,8 +23,14 @@
 namespace pic {
 
 constexpr int PBLOCK = 256;  // particle kernels
-constexpr int FX = 64;       // field tile: 64 x 4 cells of one z plane
+constexpr int FX = 64;       // default field tile: 64 x 4 cells of one z plane
 constexpr int FY = 4;
+
+// Field-kernel tile shapes (cells along x, y of one z plane per workgroup)
+// the autotuner chooses from; shape 0 is the default.
+constexpr int N_TILE_SHAPES = 8;
+constexpr int TILE_FX[N_TILE_SHAPES] = {64, 64, 128, 256, 32, 64, 128, 32};
+constexpr int TILE_FY[N_TILE_SHAPES] = {4, 2, 2, 1, 8, 8, 4, 4};
 
 struct DevState {
     int parity;      // H[parity] holds H^{n-1/2} at the start of step n
@@ -54,6 +60,7 @@ struct PmlAxis {
 
 struct FieldArgs {
     int nx, ny, nz;
+    int tile;    // tile shape index (TILE_FX / TILE_FY)
     int gx, gy;  // tiles along x and y
     int per[3];
     float S;
@@ -131,9 +138,10 @@ __device__ __forceinline__ int box_margin(int since_sort, float S)
     return 3 + (int)ceilf((float)(since_sort + 1) * S);
 }
 
-inline int field_tiles(int nx, int ny, int nz)
+inline int field_tiles(int nx, int ny, int nz, int shape = 0)
 {
-    return ((nx + FX - 1) / FX) * ((ny + FY - 1) / FY) * nz;
+    const int fx = TILE_FX[shape], fy = TILE_FY[shape];
+    return ((nx + fx - 1) / fx) * ((ny + fy - 1) / fy) * nz;
 }
 
 // Linear offset to the neighbour at distance d = +-1 along an axis of n
@@ -173,8 +181,8 @@ int scan_tmp_size(int n);
 // Batched forms: one launch over many simulations.  `args` is a device array
 // of per-simulation argument blocks; `start` a device prefix table of work
 // units (field tiles / particle workgroups) per simulation, start[n] = total.
-void launch_h_update_batch(const FieldArgs *args, const int *start, int n, int total, hipStream_t s);
-void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int total, hipStream_t s);
+void launch_h_update_batch(const FieldArgs *args, const int *start, int n, int total, int shape, hipStream_t s);
+void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int total, int shape, hipStream_t s);
 void launch_push_deposit_batch(const PartArgs *args, const int *start, int n, int total, int mode,
                                hipStream_t s);
 void launch_probe_batch(const ProbeArgs *args, int n, hipStream_t s);

@@ -57,10 +57,19 @@ class PicStats(ctypes.Structure):
                 ("pbox", ctypes.c_int32 * 6)]
 
 
-EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "pic_read_fields",
-           "pic_read_particles", "pic_diag", "pic_stats", "pic_timing", "pic_destroy",
-           "pic_last_error", "pic_batch_create", "pic_batch_step", "pic_batch_destroy",
-           "pic_batch_last_error")
+class PicTuneOut(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("fx", ctypes.c_int32), ("fy", ctypes.c_int32),
+                ("nshapes", ctypes.c_int32), ("ms", ctypes.c_double * 8)]
+
+
+EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "pic_tune",
+           "pic_read_fields", "pic_read_particles", "pic_diag", "pic_stats", "pic_timing",
+           "pic_destroy", "pic_last_error", "pic_batch_create", "pic_batch_step", "pic_batch_tune",
+           "pic_batch_destroy", "pic_batch_last_error")
+
+
+def _tune_dict(t):
+    return {"tile": t.tile, "fx": t.fx, "fy": t.fy, "ms": list(t.ms)[: t.nshapes]}
 
 _LIB = None
 
@@ -114,6 +123,10 @@ def load():
     lib.pic_batch_step.argtypes = [vp, ctypes.c_int64]
     lib.pic_batch_destroy.restype = None
     lib.pic_batch_destroy.argtypes = [vp]
+    lib.pic_tune.restype = ctypes.c_int
+    lib.pic_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(PicTuneOut)]
+    lib.pic_batch_tune.restype = ctypes.c_int
+    lib.pic_batch_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(PicTuneOut)]
     lib.pic_batch_last_error.restype = ctypes.c_char_p
     lib.pic_batch_last_error.argtypes = [vp]
     _LIB = lib
@@ -277,6 +290,12 @@ class Simulation:
         self._check(self._lib.pic_timing(self._h, _p(ms), cnt, int(bool(reset))))
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_FAMILIES)}
 
+    def tune(self, reps=20, force=-1):
+        """pic_tune: pick the field kernels' tile shape (force >= 0: that shape)."""
+        t = PicTuneOut()
+        self._check(self._lib.pic_tune(self._h, int(reps), int(force), ctypes.byref(t)))
+        return _tune_dict(t)
+
     def grad(self, omega0, nsteps, ckpt_every=0):
         """pic_grad: advance nsteps and return (L, dL/dwp, dL/dgamma), maps (nx, ny, nz)."""
         N = self.n[0] * self.n[1] * self.n[2]
@@ -342,6 +361,14 @@ class Batch:
         st = self._lib.pic_batch_step(self._h, int(n))
         if st != PIC_OK:
             raise PicError(st, self._lib.pic_batch_last_error(self._h).decode())
+
+    def tune(self, reps=10, force=-1):
+        """pic_batch_tune: one tile shape for all members' field launches."""
+        t = PicTuneOut()
+        st = self._lib.pic_batch_tune(self._h, int(reps), int(force), ctypes.byref(t))
+        if st != PIC_OK:
+            raise PicError(st, self._lib.pic_batch_last_error(self._h).decode())
+        return _tune_dict(t)
 
     def close(self):
         if getattr(self, "_h", None):

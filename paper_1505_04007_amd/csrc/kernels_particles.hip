@@ -316,9 +316,11 @@ __device__ __forceinline__ float wave_reduce64(const float *val, bool mine, int 
     return v[0];
 }
 
-// Windows summed by wavefront rounds before the remaining lanes switch to
-// per-lane atomics (a round costs about one per-lane slot loop / 4).
-constexpr int MAX_ROUNDS = 16;
+// A window shared by at least ROUND_LANES lanes is summed by a wavefront
+// round (about 220 VALU instructions, then one atomic per slot); the lanes of
+// smaller windows add their slots with per-lane atomics, all such lanes of the
+// wavefront together (54 atomic instructions however many lanes).
+constexpr int ROUND_LANES = 3;
 
 template <int MODE, int PX>
 __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
@@ -427,12 +429,17 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
         const int lrel = li + a.nx * (lj + a.ny * lk);
         float *Jl = lc == 0 ? a.Jb[0] : (lc == 1 ? a.Jb[1] : a.Jb[2]);
         const int key = (base[0] + 1) + (a.nx + 2) * ((base[1] + 1) + (a.ny + 2) * (base[2] + 1));
-        int round = 0;
-        while (rem && round < MAX_ROUNDS) {
+        unsigned long long small = 0;
+        while (rem) {
             const int leader = __ffsll((long long)rem) - 1;
             const int k0 = __builtin_amdgcn_readlane(key, leader);
             const bool mine = ((rem >> lane) & 1ull) && key == k0;
             const unsigned long long m = __ballot(mine);
+            rem &= ~m;
+            if (__popcll(m) < ROUND_LANES) {
+                small |= m;
+                continue;
+            }
             const float tot = wave_reduce64(val, mine, lane);
             const int bx = __builtin_amdgcn_readlane(base[0], leader);
             const int by = __builtin_amdgcn_readlane(base[1], leader);
@@ -443,17 +450,32 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                 float *ad = inside ? Jl + (bx + a.nx * (by + a.ny * bz)) + lrel : slot_addr(a, lane, bx, by, bz);
                 if (ad) atomicAdd(ad, tot);
             }
-            rem &= ~m;
-            ++round;
         }
+        rem = small;
     }
     if ((rem >> lane) & 1ull) {
+        const bool inside = base[0] >= 0 && base[0] + 2 < a.nx && base[1] >= 0 && base[1] + 2 < a.ny &&
+                            base[2] >= 0 && base[2] + 2 < a.nz;
+        if (inside) {
+            // slot offsets from the window's base node are uniform: one add per slot
+            const int lin = base[0] + a.nx * (base[1] + a.ny * base[2]);
+            const int sy = a.nx, sz = a.nx * a.ny;
 #pragma unroll
-        for (int s = 0; s < 54; ++s) {
-            const float v = val[s];
-            if (v != 0.f) {
-                float *ad = slot_addr(a, s, base[0], base[1], base[2]);
-                if (ad) atomicAdd(ad, v);
+            for (int s = 0; s < 54; ++s) {
+                int comp, oi, oj, ok;
+                slot_geom(s, comp, oi, oj, ok);
+                float *J = comp == 0 ? a.Jb[0] : (comp == 1 ? a.Jb[1] : a.Jb[2]);
+                const float v = val[s];
+                if (v != 0.f) atomicAdd(J + lin + (oi + sy * oj + sz * ok), v);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 54; ++s) {
+                const float v = val[s];
+                if (v != 0.f) {
+                    float *ad = slot_addr(a, s, base[0], base[1], base[2]);
+                    if (ad) atomicAdd(ad, v);
+                }
             }
         }
     }

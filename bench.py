@@ -184,7 +184,7 @@ def bench_batched(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batched16_film5-80nm_128x64x64-192x96x96", "instances": len(ws),
                       "cells": cells, "particles": sum(w.bunch.n for w in ws), "sort_every": 20,
-                      "field_tile": [tune["fx"], tune["fy"]], "parallelism": "single-gpu"},
+                      "field_tile": [tune["fx"], tune["fy"], tune["order"]], "parallelism": "single-gpu"},
            "particle_pushes_per_s": round(pushes / secs, 1),
            "plain_sequential": {"value": round(plain_g, 3), "unit": "Gcell-updates/s",
                                 "particle_pushes_per_s": round(pushes_total / plain_s, 1)},
@@ -297,8 +297,11 @@ def main():
         w.sort_every = args.sort_every
     sim = native.from_workload(w, timing=True, deposit_mode=args.deposit_mode)
     tune = sim.tune(force=0) if args.no_tune else sim.tune(reps=10)
+    if not args.no_tune:
+        print("[bench] tile variants ms per H+E pair: " + " ".join(f"{m:.3f}" for m in tune["ms"]),
+              file=sys.stderr, flush=True)
     print(f"[bench] {w.name}: {w.cells} cells, {w.bunch.n if w.bunch else 0} particles, "
-          f"warmup {args.warmup}, field tile {tune['fx']}x{tune['fy']}", file=sys.stderr, flush=True)
+          f"warmup {args.warmup}, field tile {tune['fx']}x{tune['fy']} order {tune['order']}", file=sys.stderr, flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     p0 = sim.stats()["pushes"]
@@ -352,7 +355,7 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": w.name, "cells": w.cells,
                       "particles": w.bunch.n if w.bunch else 0, "sort_every": w.sort_every,
-                      "deposit_mode": args.deposit_mode, "field_tile": [tune["fx"], tune["fy"]],
+                      "deposit_mode": args.deposit_mode, "field_tile": [tune["fx"], tune["fy"], tune["order"]],
                       "parallelism": "single-gpu"},
            "particle_pushes_per_s": round(pushes / secs, 1),
            "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 3
+#define PIC_ABI_VERSION 4
 
 typedef enum {
     PIC_OK = 0,
@@ -203,16 +203,17 @@ pic_status pic_grad(pic_ctx *ctx, double omega0, int64_t nsteps, int64_t ckpt_ev
 
 /* Result of the field-kernel tile autotuner. */
 typedef struct {
-    int32_t tile;     /* chosen tile shape index */
+    int32_t tile;     /* chosen tile variant index */
     int32_t fx, fy;   /* its cells along x and y (one z plane per workgroup) */
-    int32_t nshapes;  /* shapes in the table (entries of ms) */
-    double ms[8];     /* measured ms per H + E launch pair, per shape (0 when forced) */
+    int32_t order;    /* 0: tiles numbered x, y, z (plane by plane); 1: x, z, y */
+    int32_t nshapes;  /* variants in the table (entries of ms) */
+    double ms[16];    /* measured ms per H + E launch pair, per variant (0 when forced) */
 } pic_tune_out;
 
 /*
- * Choose the tile shape of the field kernels (H update and Drude + E
- * update) for this grid.  With force = -1, times reps H + E launch pairs of
- * every shape in the library's table on the context's stream, starting from
+ * Choose the tile shape and tile order of the field kernels (H update and
+ * Drude + E update) for this grid.  With force = -1, times reps H + E launch
+ * pairs of every variant in the library's table on the context's stream, starting from
  * the current field state and restoring it afterwards (fields, CPML
  * memories, Drude current, step clock), and keeps the fastest (the default
  * shape 0 unless another is more than 3 % faster); with force in

@@ -221,30 +221,37 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
 
 // Decompose a tile index of one simulation into (i, j, k); false when the
 // thread lies past the grid's x / y extent.
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 __device__ __forceinline__ bool tile_cell(const FieldArgs &a, int t, int &i, int &j, int &k)
 {
-    const int bx = t % a.gx, by = (t / a.gx) % a.gy;
-    k = t / (a.gx * a.gy);
+    const int bx = t % a.gx;
+    int by;
+    if (ZO) {
+        k = (t / a.gx) % a.nz;
+        by = t / (a.gx * a.nz);
+    } else {
+        by = (t / a.gx) % a.gy;
+        k = t / (a.gx * a.gy);
+    }
     i = bx * TXW + threadIdx.x;
     j = by * TYW + threadIdx.y;
     return i < a.nx && j < a.ny && k < a.nz;
 }
 
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 __global__ __launch_bounds__(TXW *TYW) void k_h_update(FieldArgs a)
 {
     int i, j, k;
-    if (!tile_cell<TXW, TYW>(a, xcd_tile(), i, j, k)) return;
+    if (!tile_cell<TXW, TYW, ZO>(a, xcd_tile(), i, j, k)) return;
     const DevState s = *a.st;
     h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
 
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 __global__ __launch_bounds__(TXW *TYW) void k_e_update(FieldArgs a)
 {
     int i, j, k;
-    if (!tile_cell<TXW, TYW>(a, xcd_tile(), i, j, k)) return;
+    if (!tile_cell<TXW, TYW, ZO>(a, xcd_tile(), i, j, k)) return;
     const DevState s = *a.st;
     e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
@@ -257,72 +264,74 @@ __device__ __forceinline__ int owner(const int *start, int n, int t)
     return q;
 }
 
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 __global__ __launch_bounds__(TXW *TYW) void k_h_update_batch(const FieldArgs *args, const int *start, int n)
 {
     const int t = xcd_tile();
     const int q = owner(start, n, t);
     const FieldArgs &a = args[q];
     int i, j, k;
-    if (!tile_cell<TXW, TYW>(a, t - start[q], i, j, k)) return;
+    if (!tile_cell<TXW, TYW, ZO>(a, t - start[q], i, j, k)) return;
     const DevState s = *a.st;
     h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
 
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 __global__ __launch_bounds__(TXW *TYW) void k_e_update_batch(const FieldArgs *args, const int *start, int n)
 {
     const int t = xcd_tile();
     const int q = owner(start, n, t);
     const FieldArgs &a = args[q];
     int i, j, k;
-    if (!tile_cell<TXW, TYW>(a, t - start[q], i, j, k)) return;
+    if (!tile_cell<TXW, TYW, ZO>(a, t - start[q], i, j, k)) return;
     const DevState s = *a.st;
     e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
 
 // One launch of a tile-shape instantiation: the shape index selects the
 // template arguments (the table in pic_internal.hpp).
-template <template <int, int> class K, typename... Args>
+template <template <int, int, int> class K, typename... Args>
 void launch_shape(int shape, int blocks, hipStream_t s, Args... args)
 {
     switch (shape) {
 #define PIC_SHAPE(v)                                                                                          \
     case v:                                                                                                   \
-        K<TILE_FX[v], TILE_FY[v]>::launch(blocks, s, args...);                                                \
+        K<TILE_FX[v], TILE_FY[v], TILE_ZO[v]>::launch(blocks, s, args...);                                    \
         break;
         PIC_SHAPE(1) PIC_SHAPE(2) PIC_SHAPE(3) PIC_SHAPE(4) PIC_SHAPE(5) PIC_SHAPE(6) PIC_SHAPE(7)
+        PIC_SHAPE(8) PIC_SHAPE(9) PIC_SHAPE(10) PIC_SHAPE(11) PIC_SHAPE(12) PIC_SHAPE(13) PIC_SHAPE(14)
+        PIC_SHAPE(15)
 #undef PIC_SHAPE
-    default: K<TILE_FX[0], TILE_FY[0]>::launch(blocks, s, args...); break;
+    default: K<TILE_FX[0], TILE_FY[0], TILE_ZO[0]>::launch(blocks, s, args...); break;
     }
 }
 
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 struct HLaunch {
     static void launch(int blocks, hipStream_t s, FieldArgs a)
     {
-        hipLaunchKernelGGL((k_h_update<TXW, TYW>), dim3(blocks), dim3(TXW, TYW), 0, s, a);
+        hipLaunchKernelGGL((k_h_update<TXW, TYW, ZO>), dim3(blocks), dim3(TXW, TYW), 0, s, a);
     }
 };
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 struct ELaunch {
     static void launch(int blocks, hipStream_t s, FieldArgs a)
     {
-        hipLaunchKernelGGL((k_e_update<TXW, TYW>), dim3(blocks), dim3(TXW, TYW), 0, s, a);
+        hipLaunchKernelGGL((k_e_update<TXW, TYW, ZO>), dim3(blocks), dim3(TXW, TYW), 0, s, a);
     }
 };
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 struct HBatchLaunch {
     static void launch(int blocks, hipStream_t s, const FieldArgs *args, const int *start, int n)
     {
-        hipLaunchKernelGGL((k_h_update_batch<TXW, TYW>), dim3(blocks), dim3(TXW, TYW), 0, s, args, start, n);
+        hipLaunchKernelGGL((k_h_update_batch<TXW, TYW, ZO>), dim3(blocks), dim3(TXW, TYW), 0, s, args, start, n);
     }
 };
-template <int TXW, int TYW>
+template <int TXW, int TYW, int ZO>
 struct EBatchLaunch {
     static void launch(int blocks, hipStream_t s, const FieldArgs *args, const int *start, int n)
     {
-        hipLaunchKernelGGL((k_e_update_batch<TXW, TYW>), dim3(blocks), dim3(TXW, TYW), 0, s, args, start, n);
+        hipLaunchKernelGGL((k_e_update_batch<TXW, TYW, ZO>), dim3(blocks), dim3(TXW, TYW), 0, s, args, start, n);
     }
 };
 

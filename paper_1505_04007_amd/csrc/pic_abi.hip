@@ -1234,6 +1234,7 @@ pic_status pic_tune(pic_ctx *c, int32_t reps, int32_t force, pic_tune_out *out)
     res.tile = c->tile;
     res.fx = pic::TILE_FX[c->tile];
     res.fy = pic::TILE_FY[c->tile];
+    res.order = pic::TILE_ZO[c->tile];
     if (out) *out = res;
     return PIC_OK;
 }
@@ -1700,6 +1701,7 @@ pic_status pic_batch_tune(pic_batch *b, int32_t reps, int32_t force, pic_tune_ou
     res.tile = best;
     res.fx = pic::TILE_FX[best];
     res.fy = pic::TILE_FY[best];
+    res.order = pic::TILE_ZO[best];
     if (out) *out = res;
     return PIC_OK;
 }

@@ -27,10 +27,14 @@ constexpr int FX = 64;       // default field tile: 64 x 4 cells of one z plane
 constexpr int FY = 4;
 
 // Field-kernel tile shapes (cells along x, y of one z plane per workgroup)
-// the autotuner chooses from; shape 0 is the default.
-constexpr int N_TILE_SHAPES = 8;
-constexpr int TILE_FX[N_TILE_SHAPES] = {64, 64, 128, 256, 32, 64, 128, 32};
-constexpr int TILE_FY[N_TILE_SHAPES] = {4, 2, 2, 1, 8, 8, 4, 4};
+// and tile orders the autotuner chooses from; shape 0 is the default.
+// Order 0 numbers tiles x, then y, then z (a plane at a time); order 1 x,
+// then z, then y (a band of rows marches through all planes, so the next
+// plane's values are still in L2 when its tiles run).
+constexpr int N_TILE_SHAPES = 16;
+constexpr int TILE_FX[N_TILE_SHAPES] = {64, 64, 128, 256, 32, 64, 128, 32, 64, 64, 128, 256, 32, 64, 128, 32};
+constexpr int TILE_FY[N_TILE_SHAPES] = {4, 2, 2, 1, 8, 8, 4, 4, 4, 2, 2, 1, 8, 8, 4, 4};
+constexpr int TILE_ZO[N_TILE_SHAPES] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1};
 
 struct DevState {
     int parity;      // H[parity] holds H^{n-1/2} at the start of step n

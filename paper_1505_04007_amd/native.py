@@ -59,7 +59,7 @@ class PicStats(ctypes.Structure):
 
 class PicTuneOut(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("fx", ctypes.c_int32), ("fy", ctypes.c_int32),
-                ("nshapes", ctypes.c_int32), ("ms", ctypes.c_double * 8)]
+                ("order", ctypes.c_int32), ("nshapes", ctypes.c_int32), ("ms", ctypes.c_double * 16)]
 
 
 EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "pic_tune",
@@ -69,7 +69,7 @@ EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "
 
 
 def _tune_dict(t):
-    return {"tile": t.tile, "fx": t.fx, "fy": t.fy, "ms": list(t.ms)[: t.nshapes]}
+    return {"tile": t.tile, "fx": t.fx, "fy": t.fy, "order": t.order, "ms": list(t.ms)[: t.nshapes]}
 
 _LIB = None
 

@@ -12,7 +12,7 @@ from paper_1505_04007_amd import native
 
 pytestmark = pytest.mark.gpu
 
-NSHAPES = 8
+NSHAPES = 16
 
 
 def _ragged(bc, npml):
@@ -97,7 +97,7 @@ def test_batch_tune_keeps_members_equal_to_plain_runs():
         for s, p in zip(sims, plain):
             for x, y in zip(_fields(s), _fields(p)):
                 assert np.array_equal(x, y)
-        b.tune(force=3)
+        b.tune(force=11)
         b.close()
 
 

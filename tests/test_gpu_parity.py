@@ -284,3 +284,39 @@ def test_full_size_workloads_conserve_charge(make, steps):
     assert d["gauss_max"] <= 5e-5 * d["rho0_max"], d
     F = g.probe()
     assert np.all(np.isfinite(F))
+
+
+@pytest.mark.parametrize("ny", [1, 2, 3])
+def test_thin_periodic_axis_with_bunch_matches_oracle(ny):
+    """Degenerate grids: one, two or three periodic cells across y (a 2-D
+    sheet problem, as in the paper's geometry).  A deposit window spans three
+    nodes, so it wraps onto itself once or twice."""
+    nx, nz, dx = 30, 22, 4e-9
+    wpm, gm = pi.film_maps(nx, ny, nz, 5, 9)
+    rng = np.random.default_rng(pi.SEED0 + 50 + ny)
+    b = pi.gaussian_bunch(rng, 400, (9 * dx, ny * dx / 2, 13 * dx), (1.5 * dx, ny * dx, 1.5 * dx), 60e3)
+    b.y = np.mod(b.y, ny * dx)
+    w = pi.Workload(f"sheet_ny{ny}", nx, ny, nz, dx, pi.courant_dt(dx),
+                    (native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, wpm, gm, b,
+                    np.array([[18 * dx, 0.0, 9.6 * dx]]), pi.spectrum_omegas(nfreq=8), 80)
+    o = _oracle_of(w)
+    g = _gpu_of(w, sort_every=9)
+    o.step(80)
+    g.step(80)
+    _compare_fields(g, o, (nx, ny, nz), 1e-3)
+    _moments_close(g.diag(), o.diag(), dx, 1e-3)
+    assert _rel(g.probe(), o.probe()) <= 1e-3
+
+
+def test_minimum_pec_grid_fields_only():
+    """Two cells per axis between PEC walls: only a handful of edges move."""
+    n, dx = (2, 2, 2), 5e-9
+    wpm, gm = pi.film_maps(*n, 0, 1)
+    w = pi.Workload("pec_2x2x2", *n, dx, pi.courant_dt(dx), (native.BC_PEC,) * 3, 0, wpm, gm, None,
+                    np.array([[dx, dx, 0.5 * dx]]), pi.spectrum_omegas(nfreq=4), 50)
+    Efull = pi.sample_field(pi.CavityField(np.array(n) * dx, seed=5, amplitude=1e5), "E", n, dx)
+    o = _oracle_of(w, Efull)
+    g = _gpu_of(w, Efull)
+    o.step(50)
+    g.step(50)
+    _compare_fields(g, o, n, 1e-5)

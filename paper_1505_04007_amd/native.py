@@ -285,8 +285,8 @@ class Simulation:
         return {"steps": s.steps, "pushes": s.pushes, "live": s.live, "pbox": tuple(s.pbox)}
 
     def timing(self, reset=False):
-        ms = np.zeros(5)
-        cnt = (ctypes.c_int64 * 5)()
+        ms = np.zeros(len(KERNEL_FAMILIES))
+        cnt = (ctypes.c_int64 * len(KERNEL_FAMILIES))()
         self._check(self._lib.pic_timing(self._h, _p(ms), cnt, int(bool(reset))))
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_FAMILIES)}
 

@@ -30,6 +30,19 @@ def test_library_exports_every_declared_entry_point():
     assert lib.pic_abi_version() == ver
 
 
+def test_binding_structs_and_buffers_match_the_header():
+    """The ctypes mirrors of pic_opts and of pic_timing's output arrays have the
+    header's field count and length (a short buffer is overrun by the library)."""
+    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+    n_fam = int(re.search(r"ms_total\[(\d+)\], launches\[(\d+)\]", src).group(1))
+    assert n_fam == len(native.KERNEL_FAMILIES)
+    end = src.index("} pic_opts;")
+    body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"): end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(\w+)(?:\[\d+\])?\s*;", body)
+    assert fields == [f[0] for f in native.PicOpts._fields_]
+
+
 def _init(**over):
     lib = native.load()
     w = pi.slab_tiny(with_bunch=False)

@@ -608,9 +608,37 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
         }
     }
     __syncthreads();
-    if (threadIdx.x < 3 && bb[threadIdx.x] != INT_MAX) atomicMin(&a.box[threadIdx.x], bb[threadIdx.x]);
-    if (threadIdx.x >= 3 && threadIdx.x < 6 && bb[threadIdx.x] != INT_MIN)
-        atomicMax(&a.box[threadIdx.x], bb[threadIdx.x]);
+    // one partial box per workgroup (global atomics from every workgroup on
+    // the same six words would serialise); k_box_reduce combines them
+    if (threadIdx.x < 6) a.boxpart[blockIdx.x * 6 + threadIdx.x] = bb[threadIdx.x];
+}
+
+// The live-cell box from the count workgroups' partial boxes (one workgroup).
+constexpr int BOX_THREADS = 256;
+__global__ __launch_bounds__(BOX_THREADS) void k_box_reduce(SortArgs a, int nparts)
+{
+    __shared__ int red[6][BOX_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int v[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+    for (int w = threadIdx.x; w < nparts; w += BOX_THREADS) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            v[q] = min(v[q], a.boxpart[w * 6 + q]);
+            v[3 + q] = max(v[3 + q], a.boxpart[w * 6 + 3 + q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        v[q] = q < 3 ? wave_minmax<false>(v[q]) : wave_minmax<true>(v[q]);
+        if (lane == 0) red[q][wave] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int q = threadIdx.x;
+        int r = red[q][0];
+        for (int w = 1; w < BOX_THREADS / 64; ++w) r = q < 3 ? min(r, red[q][w]) : max(r, red[q][w]);
+        a.box[q] = r;
+    }
 }
 
 // Three-phase exclusive scan over SCAN_ITEMS * SCAN_THREADS elements per block.
@@ -710,11 +738,13 @@ void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s)
 {
     const int ncount = a.ncell + 1;
     launch_fill_i32(a.counts, 0, ncount, s);
-    launch_fill_i32(a.box, INT_MAX, 3, s);
-    launch_fill_i32(a.box + 3, INT_MIN, 3, s);
     if (a.n > 0) {
         const int nb = (a.n + PBLOCK - 1) / PBLOCK;
         hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(PBLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(BOX_THREADS), 0, s, a, nb);
+    } else {
+        launch_fill_i32(a.box, INT_MAX, 3, s);
+        launch_fill_i32(a.box + 3, INT_MIN, 3, s);
     }
     const int ntiles = (ncount + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(SCAN_THREADS), 0, s, a.counts, ncount, scan_tmp);

@@ -67,6 +67,7 @@ struct pic_ctx {
     int *pid[2] = {nullptr, nullptr};
     int pcur = 0;
     int *key = nullptr, *rank = nullptr, *counts = nullptr, *box = nullptr, *scan_tmp = nullptr;
+    int *boxpart = nullptr;  // per-workgroup partial boxes of the sort's count kernel
     int scan_len = 0;
     float ah = 0.f, qd = 0.f;
     double q = 0, m = 0, w = 0;
@@ -233,6 +234,7 @@ void build_args(pic_ctx *c)
     sa.rank = c->rank;
     sa.counts = c->counts;
     sa.box = c->box;
+    sa.boxpart = c->boxpart;
     sa.st = c->dstate;
 
     pic::ProbeArgs &pr = c->pr;
@@ -650,6 +652,7 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         TRY(dalloc(c, &c->rank, (size_t)c->np));
         TRY(dalloc(c, &c->counts, (size_t)ncell + 1));
         TRY(dalloc(c, &c->box, 6));
+        TRY(dalloc(c, &c->boxpart, 6 * (((size_t)c->np + pic::PBLOCK - 1) / pic::PBLOCK)));
         c->scan_len = pic::scan_tmp_size((int)ncell + 1);
         TRY(dalloc(c, &c->scan_tmp, (size_t)c->scan_len));
         for (int d = 0; d < 3; ++d) {

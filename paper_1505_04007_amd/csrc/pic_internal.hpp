@@ -107,7 +107,8 @@ struct SortArgs {
     int *key;
     int *rank;
     int *counts;  // [ncell + 1]
-    int *box;     // [6] bounding box of live cells, written by the count kernel
+    int *box;     // [6] bounding box of live cells (lo x, y, z, hi x, y, z)
+    int *boxpart; // [6 * count workgroups] each count workgroup's box, reduced into box
     DevState *st;
 };
 

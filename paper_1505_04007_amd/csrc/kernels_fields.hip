@@ -27,6 +27,12 @@ __device__ __forceinline__ int lin(const FieldArgs &a, int i, int j, int k)
     return i + a.nx * (j + a.ny * k);
 }
 
+// Values a cell reads or writes once, that no neighbour touches in the same
+// launch, are streamed past the caches so they keep the stencil's shared
+// neighbour data.
+__device__ __forceinline__ float ld_once(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_once(float *p, float v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ float cpml(float *__restrict__ psi, int sid, float b, float c, float ik,
                                       float d)
 {
@@ -75,7 +81,7 @@ __device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, 
     float eyx = Ey[id + ox], ezx = Ez[id + ox];
     float exy = Ex[id + oy], ezy = Ez[id + oy];
     float exz = Ex[id + oz], eyz = Ey[id + oz];
-    const float hx = H0[id], hy = H1[id], hz = H2[id];
+    const float hx = ld_once(H0 + id), hy = ld_once(H1 + id), hz = ld_once(H2 + id);
     eyx = okx ? eyx : 0.f;
     ezx = okx ? ezx : 0.f;
     exy = oky ? exy : 0.f;
@@ -116,9 +122,9 @@ __device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, 
     const float nhx = hx - S * (dyEz - dzEy);
     const float nhy = hy - S * (dzEx - dxEz);
     const float nhz = hz - S * (dxEy - dyEx);
-    O0[id] = nhx;
-    O1[id] = nhy;
-    O2[id] = nhz;
+    st_once(O0 + id, nhx);
+    st_once(O1 + id, nhy);
+    st_once(O2 + id, nhz);
     if (a.Havg[0] && in_particle_box(a, margin, i, j, k)) {
         // B^n of the push, (Ht^{n-1/2} + Ht^{n+1/2})/2, where particles can gather it
         a.Havg[0][id] = 0.5f * (hx + nhx);
@@ -147,7 +153,7 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
     float hyx = Hy[id + ox], hzx = Hz[id + ox];
     float hxy = Hx[id + oy], hzy = Hz[id + oy];
     float hxz = Hx[id + oz], hyz = Hy[id + oz];
-    const float ex = a.E[0][id], ey = a.E[1][id], ez = a.E[2][id];
+    const float ex = ld_once(a.E[0] + id), ey = ld_once(a.E[1] + id), ez = ld_once(a.E[2] + id);
     hyx = okx ? hyx : 0.f;
     hzx = okx ? hzx : 0.f;
     hxy = oky ? hxy : 0.f;
@@ -213,9 +219,9 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
         a.Jb[2][id] = 0.f;
     }
     const bool wx = !a.per[0] && i == 0, wy = !a.per[1] && j == 0, wz = !a.per[2] && k == 0;
-    if (!(wy || wz)) a.E[0][id] = nex;
-    if (!(wx || wz)) a.E[1][id] = ney;
-    if (!(wx || wy)) a.E[2][id] = nez;
+    if (!(wy || wz)) st_once(a.E[0] + id, nex);
+    if (!(wx || wz)) st_once(a.E[1] + id, ney);
+    if (!(wx || wy)) st_once(a.E[2] + id, nez);
     if (!(isfinite(nex) && isfinite(ney) && isfinite(nez))) atomicOr(a.nan_flag, 1);
 }
 

@@ -133,6 +133,33 @@ def test_lossless_plasma_oscillation_closed_form(oracle_mod):
     assert abs(th / (wp * dt) - 1) < wpdt ** 2 / 24 * 1.01
 
 
+def test_damped_drude_mode_follows_eq6_eq8_recurrence(oracle_mod):
+    """k = 0 mode of a collisional Drude medium, exactly (round-off).
+
+    With curl H = 0, Eq. 6 (J^{n+1/2} = ca J^{n-1/2} + cb E^n, ca = (2 - g dt)/(2 + g dt),
+    cb = 2 dt eps0 wp^2/(2 + g dt)) and Eq. 8 (E^{n+1} = E^n - (dt/eps0) J^{n+1/2})
+    form a 2x2 linear map of (E^n, J^{n-1/2}); iterated in FP64 from J^{-1/2} = 0 it
+    must reproduce the oracle's uniform field step by step.  A different time
+    level of E in Eq. 6, or a wrong ca / cb, changes the sequence at first order.
+    """
+    po = oracle_mod
+    _, _, eps0 = _consts(po)
+    wp, wpdt = 1.3e16, 0.05
+    gamma = 0.3 * wp
+    E, dt = _uniform_plasma(po, wp, gamma, wpdt, 600)
+    ca = (2 - gamma * dt) / (2 + gamma * dt)
+    cb = 2 * dt * eps0 * wp ** 2 / (2 + gamma * dt)
+    e, j = 1.0, 0.0
+    ref = [e]
+    for _ in range(E.size - 1):
+        j = ca * j + cb * e
+        e = e - dt / eps0 * j
+        ref.append(e)
+    ref = np.array(ref)
+    assert np.abs(E - ref).max() < 1e-12
+    assert np.abs(ref).min() < 0.5  # the mode does oscillate and decay over the run
+
+
 def _fit_recurrence(E):
     """Least-squares (p, q) of E^{n+1} = p E^n - q E^{n-1}."""
     Amat = np.stack([E[1:-1], -E[:-2]], axis=1)

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 4
+#define PIC_ABI_VERSION 5
 
 typedef enum {
     PIC_OK = 0,
@@ -96,6 +96,22 @@ typedef struct {
     double q, m, weight;
 } pic_particles;
 
+/*
+ * Optional caller-owned device memory for the field arrays (for example
+ * PyTorch tensors), each nx*ny*nz FP32 values in the compact Yee layout
+ * (x fastest), 4-byte aligned, not overlapping one another.  A NULL entry is
+ * allocated by the library.  Borrowed: the memory must outlive the context;
+ * pic_destroy does not free it.  pic_init overwrites it with the initial
+ * state.  E holds E in V/m; H[p] holds eta0 H (V/m) for the two time levels
+ * of the H update's ping-pong, H[hcur] (pic_stats) being H^{n-1/2}.  The
+ * library writes them asynchronously on the context's stream; readers order
+ * their work after it on that stream.
+ */
+typedef struct {
+    float *E[3];
+    float *H[2][3];
+} pic_device_buffers;
+
 typedef struct {
     void *stream;             /* hipStream_t; NULL = default stream */
     int32_t nprobe;           /* Ez probes (nearest Ez node, ties toward +z) */
@@ -112,6 +128,7 @@ typedef struct {
     int32_t diag;             /* 1: keep the FP64 charge grid needed by the Gauss check */
     int32_t timing;           /* 1: time every kernel launch with HIP events */
     int32_t deposit_mode;     /* 0: wavefront-reduced deposit (default), 1: per-lane atomics */
+    const pic_device_buffers *bufs;  /* optional caller device memory for E and H; NULL = none */
 } pic_opts;
 
 typedef struct pic_ctx pic_ctx;
@@ -133,6 +150,7 @@ typedef struct {
     int64_t live;         /* live particles now */
     int32_t pbox[6];      /* cell bounding box of the live particles at the last sort:
                              lo x, y, z, hi x, y, z (inclusive); hi < lo when empty */
+    int32_t hcur;         /* which H buffer (0 or 1) holds H^{n-1/2} for the next step */
 } pic_stats_out;
 
 /* Library ABI version (PIC_ABI_VERSION). */

@@ -457,12 +457,34 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
             }
     }
 
-    // ---- device allocations ----
+    // ---- device allocations (E and H may come from the caller) ----
     const size_t N = (size_t)ncell;
+    if (o.bufs) {
+        const float *given[9];
+        int ng = 0;
+        for (int d = 0; d < 3; ++d) {
+            given[ng++] = o.bufs->E[d];
+            given[ng++] = o.bufs->H[0][d];
+            given[ng++] = o.bufs->H[1][d];
+        }
+        for (int q = 0; q < ng; ++q) {
+            if (!given[q]) continue;
+            if ((uintptr_t)given[q] % 4 != 0) return fail(c, PIC_EINVAL, "bufs: field pointer %d is not 4-byte aligned", q);
+            for (int r = 0; r < q; ++r)
+                if (given[r] && given[r] < given[q] + N && given[q] < given[r] + N)
+                    return fail(c, PIC_EINVAL, "bufs: field arrays %d and %d overlap", r, q);
+        }
+    }
     for (int d = 0; d < 3; ++d) {
-        TRY(dalloc(c, &c->E[d], N));
-        TRY(dalloc(c, &c->H[0][d], N));
-        TRY(dalloc(c, &c->H[1][d], N));
+        float *gE = o.bufs ? o.bufs->E[d] : nullptr;
+        float *gH0 = o.bufs ? o.bufs->H[0][d] : nullptr;
+        float *gH1 = o.bufs ? o.bufs->H[1][d] : nullptr;
+        if (gE) c->E[d] = gE;
+        else TRY(dalloc(c, &c->E[d], N));
+        if (gH0) c->H[0][d] = gH0;
+        else TRY(dalloc(c, &c->H[0][d], N));
+        if (gH1) c->H[1][d] = gH1;
+        else TRY(dalloc(c, &c->H[1][d], N));
         HIP_TRY(c, hipMemsetAsync(c->E[d], 0, N * 4, c->stream));
         HIP_TRY(c, hipMemsetAsync(c->H[0][d], 0, N * 4, c->stream));
         HIP_TRY(c, hipMemsetAsync(c->H[1][d], 0, N * 4, c->stream));
@@ -1353,6 +1375,7 @@ pic_status pic_stats(pic_ctx *c, pic_stats_out *out)
     }
     out->steps = c->step;
     out->pushes = (int64_t)pushes;
+    out->hcur = c->hcur;
     out->live = 0;
     for (int d = 0; d < 3; ++d) {
         out->pbox[d] = 0;

@@ -37,12 +37,17 @@ class PicParticles(ctypes.Structure):
                 ("q", ctypes.c_double), ("m", ctypes.c_double), ("weight", ctypes.c_double)]
 
 
+class PicDeviceBuffers(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_void_p * 3), ("H", (ctypes.c_void_p * 3) * 2)]
+
+
 class PicOpts(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("nprobe", ctypes.c_int32), ("probe_xyz", _dp),
                 ("nfreq", ctypes.c_int32), ("omega", _dp), ("series_len", ctypes.c_int64),
                 ("sort_every", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("init_E", _dp * 3), ("init_H", _dp * 3), ("diag", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("deposit_mode", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("deposit_mode", ctypes.c_int32),
+                ("bufs", ctypes.POINTER(PicDeviceBuffers))]
 
 
 class PicDiag(ctypes.Structure):
@@ -54,7 +59,7 @@ class PicDiag(ctypes.Structure):
 
 class PicStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("pushes", ctypes.c_int64), ("live", ctypes.c_int64),
-                ("pbox", ctypes.c_int32 * 6)]
+                ("pbox", ctypes.c_int32 * 6), ("hcur", ctypes.c_int32)]
 
 
 class PicTuneOut(ctypes.Structure):
@@ -174,13 +179,18 @@ class Simulation:
     Arguments mirror pic_init: grid sizes/boundaries, cell size dx (m), time
     step dt (s), per-cell Drude maps (nx, ny, nz) in rad/s and 1/s, an
     optional bunch, probe positions (m) and DFT frequencies (rad/s).
+
+    device_fields=True: E and both H levels live in torch tensors this object
+    allocates (pic_opts.bufs), readable on the GPU without copies through
+    device_E() and device_H().
     """
 
     def __init__(self, nx, ny, nz, dx, dt, wp_map, gamma_map, bc=(BC_PEC,) * 3, npml=0,
                  pml=(3.0, 1.0, 1.0, 0.0), bunch=None, probes=None, omega=None, series_len=0,
                  sort_every=0, check_every=0, init_E=None, init_H=None, diag=False, timing=False,
-                 deposit_mode=0, stream=None):
+                 deposit_mode=0, device_fields=False, stream=None):
         self._lib = load()
+        self._E_dev = self._H_dev = None
         self.n = (int(nx), int(ny), int(nz))
         self.dx, self.dt = float(dx), float(dt)
         g = PicGrid(nx, ny, nz, (ctypes.c_int32 * 3)(*[int(b) for b in bc]), int(npml), *pml)
@@ -222,6 +232,18 @@ class Simulation:
         o.diag = int(bool(diag))
         o.timing = int(bool(timing))
         o.deposit_mode = int(deposit_mode)
+        if device_fields:
+            import torch
+            shape = (int(nz), int(ny), int(nx))
+            self._E_dev = torch.empty((3,) + shape, dtype=torch.float32, device="cuda")
+            self._H_dev = torch.empty((2, 3) + shape, dtype=torch.float32, device="cuda")
+            bufs = PicDeviceBuffers()
+            for d in range(3):
+                bufs.E[d] = self._E_dev[d].data_ptr()
+                for p in range(2):
+                    bufs.H[p][d] = self._H_dev[p, d].data_ptr()
+            self._keep.append(bufs)
+            o.bufs = ctypes.pointer(bufs)
         h = ctypes.c_void_p()
         st = self._lib.pic_init(ctypes.byref(h), ctypes.byref(g), self.dx, self.dt, _p(wp),
                                 _p(gm), ctypes.byref(parts) if parts is not None else None,
@@ -282,7 +304,21 @@ class Simulation:
     def stats(self):
         s = PicStats()
         self._check(self._lib.pic_stats(self._h, ctypes.byref(s)))
-        return {"steps": s.steps, "pushes": s.pushes, "live": s.live, "pbox": tuple(s.pbox)}
+        return {"steps": s.steps, "pushes": s.pushes, "live": s.live, "pbox": tuple(s.pbox), "hcur": s.hcur}
+
+    def device_E(self):
+        """E (V/m) as a torch tensor (3, nz, ny, nx) on the GPU, the library's own
+        storage (device_fields=True); ordered after the steps on the context's stream."""
+        if self._E_dev is None:
+            raise PicError(PIC_EINVAL, "created without device_fields=True")
+        return self._E_dev
+
+    def device_H(self):
+        """eta0 H (V/m) at the current half step, (3, nz, ny, nx), the library's own
+        storage (device_fields=True)."""
+        if self._H_dev is None:
+            raise PicError(PIC_EINVAL, "created without device_fields=True")
+        return self._H_dev[self.stats()["hcur"]]
 
     def timing(self, reset=False):
         ms = np.zeros(len(KERNEL_FAMILIES))

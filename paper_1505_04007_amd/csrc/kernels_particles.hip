@@ -614,7 +614,7 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
 }
 
 // The live-cell box from the count workgroups' partial boxes (one workgroup).
-constexpr int BOX_THREADS = 256;
+constexpr int BOX_THREADS = 1024;
 __global__ __launch_bounds__(BOX_THREADS) void k_box_reduce(SortArgs a, int nparts)
 {
     __shared__ int red[6][BOX_THREADS / 64];
@@ -695,21 +695,44 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(int *tile_sums, int 
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int *data, int n, const int *tile_sums)
 {
     __shared__ int sm[SCAN_THREADS];
-    // each thread owns SCAN_ITEMS consecutive elements of the tile
+    // each thread owns SCAN_ITEMS consecutive elements of the tile, moved as
+    // 16-byte vectors where the whole group lies inside the array
+    static_assert(SCAN_ITEMS % 4 == 0, "vector groups of 4");
     const long long b0 = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    const bool full = b0 + SCAN_ITEMS <= n;
     int vals[SCAN_ITEMS];
-    int s = 0;
-    for (int q = 0; q < SCAN_ITEMS; ++q) {
-        const long long idx = b0 + q;
-        vals[q] = idx < n ? data[idx] : 0;
-        s += vals[q];
+    if (full) {
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS; q += 4) {
+            const int4 v = *reinterpret_cast<const int4 *>(data + b0 + q);
+            vals[q] = v.x;
+            vals[q + 1] = v.y;
+            vals[q + 2] = v.z;
+            vals[q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS; ++q) vals[q] = b0 + q < n ? data[b0 + q] : 0;
     }
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) s += vals[q];
     int total;
     int run = block_exclusive_scan(s, sm, total) + tile_sums[blockIdx.x];
+    int outv[SCAN_ITEMS];
+#pragma unroll
     for (int q = 0; q < SCAN_ITEMS; ++q) {
-        const long long idx = b0 + q;
-        if (idx < n) data[idx] = run;
+        outv[q] = run;
         run += vals[q];
+    }
+    if (full) {
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS; q += 4)
+            *reinterpret_cast<int4 *>(data + b0 + q) = make_int4(outv[q], outv[q + 1], outv[q + 2], outv[q + 3]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS; ++q)
+            if (b0 + q < n) data[b0 + q] = outv[q];
     }
 }
 

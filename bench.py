@@ -220,6 +220,11 @@ def bench_adjoint(args):
     plain.close()
     print(f"[bench] plain {N} steps: {tf:.3f} s", file=sys.stderr, flush=True)
     sim = native.from_workload(w)
+    # pic_grad's automatic choice: every step's metal-box snapshot kept from the
+    # forward run when they fit in half the free memory, else sqrt(N) checkpoints
+    free_b, _ = torch.cuda.mem_get_info()
+    replay = ("snapshots of every step, no replay" if N * 24 * metal_box_cells(w) <= free_b / 2
+              else f"checkpoints every {int(np.ceil(np.sqrt(N)))} steps, replayed")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     L, gw, gg = sim.grad(w0, N)
@@ -233,7 +238,7 @@ def bench_adjoint(args):
            "data": "synthetic",
            "config": {"workload": w.name + "_adjoint", "cells": w.cells, "particles": w.bunch.n,
                       "sort_every": w.sort_every, "objective": "sum_p |F_p(0.68 wp)|^2",
-                      "ckpt_every": int(np.ceil(np.sqrt(N))), "parallelism": "single-gpu"},
+                      "reverse_pass": replay, "parallelism": "single-gpu"},
            "plain_forward": {"value": round(w.cells * N / tf / 1e9, 3), "unit": "Gcell-updates/s",
                              "seconds": round(tf, 4), "particle_pushes_per_s": round(pushes / tf, 1)},
            "grad_seconds": round(tg, 4),

@@ -197,14 +197,19 @@ pic_status pic_probe(pic_ctx *ctx, double *re, double *im, double *series);
  * at the values this run deposits (the current is recorded and prescribed;
  * the field's back-action on the bunch is not differentiated).
  *
- * Method: the forward run stores a field checkpoint every ckpt_every steps
- * (0: ceil(sqrt(nsteps))) and the bunch current of every step on its
- * particle box; the reverse pass replays each segment from its checkpoint
- * with the recorded current and runs the transposed field + Drude + CPML
- * step back through it, accumulating the gradient in FP64.  Device memory
- * is allocated for the call and released before it returns: about
- * (nsteps/ckpt_every + 1) field states, the recorded current, ckpt_every
- * metal-box snapshots and one adjoint field state.
+ * Method: the reverse pass runs the transposed field + Drude + CPML step
+ * back through the run, accumulating the gradient in FP64; it needs E^n and
+ * J^{n-1/2} on the metal box at every step.  With ckpt_every = 0 and
+ * nsteps * 24 bytes per metal-box cell within half the free device memory,
+ * the forward run keeps those snapshots for every step and nothing is
+ * replayed.  Otherwise (ckpt_every > 0, or 0 when they do not fit:
+ * ceil(sqrt(nsteps))) the forward run stores a field checkpoint every
+ * ckpt_every steps and the bunch current of every step on its particle box,
+ * and the reverse pass replays each segment from its checkpoint with the
+ * recorded current.  Both give the same result.  Device memory is allocated
+ * for the call and released before it returns: the snapshots and one
+ * adjoint field state, plus with checkpoints about (nsteps/ckpt_every + 1)
+ * field states and the recorded current.
  *
  *   omega0     : rad/s
  *   L          : out, V^2 s^2 / m^2

@@ -905,21 +905,39 @@ pic_status arena_take(pic_ctx *c, GradScratch &g, Arena &ar, size_t count, float
     return PIC_OK;
 }
 
-pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double *L, double *dL_dwp,
-                     double *dL_dgamma)
+// The adjoint reads, for every step, E^n and J^{n-1/2} on the metal box
+// (the Drude gradient's factors).  store_all: the forward run keeps that
+// snapshot for every step and the reverse pass needs no replay; otherwise
+// it keeps a field checkpoint every K steps and the bunch current of every
+// step, and the reverse pass replays each segment to regenerate them.
+pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, bool store_all, double *L,
+                     double *dL_dwp, double *dL_dgamma)
 {
     const size_t ncell = (size_t)c->n[0] * c->n[1] * c->n[2];
     const int npr = c->nprobe;
     const double dt = c->dt;
+    if (store_all) K = N;
     const long long nseg = (N + K - 1) / K;
     const long long s0 = c->step;
     GradScratch g;
     g.s = c->stream;
 
-    // ---- forward run: checkpoints every K steps, bunch current, probe Ez ----
+    pic::TrajArgs ta{};
+    for (int d = 0; d < 3; ++d) {
+        ta.E[d] = c->E[d];
+        ta.Jp[d] = c->Jp[d];
+        ta.mlo[d] = c->mlo[d];
+        ta.w[d] = c->mhi[d] - c->mlo[d];
+    }
+    ta.nx = c->n[0];
+    ta.ny = c->n[1];
+    float *traj = nullptr;  // metal-box snapshots: one per step of a segment, or of the run
+    TRY(galloc(c, g, &traj, (size_t)K * 6 * c->nbox));
+
+    // ---- forward run: snapshots or checkpoints + bunch current, probe Ez ----
     const size_t ckb = state_bytes(c);
     char *ck = nullptr;
-    TRY(galloc(c, g, &ck, ckb * (size_t)(nseg + 1)));
+    if (!store_all) TRY(galloc(c, g, &ck, ckb * (size_t)(nseg + 1)));
     std::vector<Mirror> mir((size_t)nseg + 1);
     double *gser = nullptr;
     TRY(galloc(c, g, &gser, (size_t)N * npr));
@@ -933,6 +951,14 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double
     bool have_box = false;
     pic_status st = PIC_OK;
     for (long long r = 0; r < N && st == PIC_OK; ++r) {
+        if (store_all) {
+            if (c->has_metal) {
+                ta.out = traj + (size_t)r * 6 * c->nbox;
+                pic::launch_traj_store(ta, c->stream);
+            }
+            st = step_once(c);
+            continue;
+        }
         if (r % K == 0) st = ckpt_save(c, ck + (size_t)(r / K) * ckb, mir[(size_t)(r / K)]);
         if (st != PIC_OK) break;
         if (c->np <= 0) {
@@ -1013,8 +1039,8 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double
 
     // ---- adjoint state (seeds scaled by 1/sigma, so the adjoint is O(1) in FP32) ----
     Mirror endm{};
-    char *endck = ck + (size_t)nseg * ckb;
-    TRY(ckpt_save(c, endck, endm));
+    char *endck = store_all ? nullptr : ck + (size_t)nseg * ckb;
+    if (!store_all) TRY(ckpt_save(c, endck, endm));
     std::vector<float> seedf(seed.size());
     for (size_t q = 0; q < seed.size(); ++q) seedf[q] = (float)(seed[q] / sigma);
     float *dseed = nullptr;
@@ -1059,8 +1085,6 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double
     HIP_TRY(c, hipMemsetAsync(aa.gd, 0, c->nbox * 8, c->stream));
     aa.nprobe = npr;
     aa.pidx = c->pidx;
-    float *traj = nullptr;
-    TRY(galloc(c, g, &traj, (size_t)K * 6 * c->nbox));
 
     // replay: fields only, bunch current from the record, E update reading
     // and clearing it over the whole grid, probes not accumulated
@@ -1079,15 +1103,6 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double
     pq.nfreq = 0;
     pq.series = nullptr;
     pq.gser = nullptr;
-    pic::TrajArgs ta{};
-    for (int d = 0; d < 3; ++d) {
-        ta.E[d] = c->E[d];
-        ta.Jp[d] = c->Jp[d];
-        ta.mlo[d] = c->mlo[d];
-        ta.w[d] = c->mhi[d] - c->mlo[d];
-    }
-    ta.nx = c->n[0];
-    ta.ny = c->n[1];
 
     // dL/dE^{s0+N} and the CPML weights of the last step's E update
     aa.mode = 2;
@@ -1096,8 +1111,8 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double
     pic::launch_adj_edge(aa, c->stream);
     for (long long j = nseg - 1; j >= 0; --j) {
         const long long a0 = j * K, b0 = std::min(N, a0 + K);
-        TRY(ckpt_load(c, ck + (size_t)j * ckb, mir[(size_t)j]));
-        for (long long r = a0; r < b0; ++r) {
+        if (!store_all) TRY(ckpt_load(c, ck + (size_t)j * ckb, mir[(size_t)j]));
+        for (long long r = a0; r < b0 && !store_all; ++r) {
             ta.out = traj + (size_t)(r - a0) * 6 * c->nbox;
             pic::launch_traj_store(ta, c->stream);
             pic::launch_h_update(fr, c->stream);
@@ -1131,7 +1146,7 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, double
         }
         HIP_TRY(c, hipGetLastError());
     }
-    TRY(ckpt_load(c, endck, endm));
+    if (!store_all) TRY(ckpt_load(c, endck, endm));
 
     // ---- chain rule to (wp, gamma) per cell, FP64 on the host ----
     std::vector<double> gcb(c->nbox), gd(c->nbox);
@@ -1233,7 +1248,16 @@ pic_status pic_grad(pic_ctx *c, double omega0, int64_t nsteps, int64_t ckpt_ever
     if (c->nprobe < 1) return fail(c, PIC_EINVAL, "pic_grad needs at least one probe");
     long long K = ckpt_every > 0 ? (long long)ckpt_every : (long long)std::ceil(std::sqrt((double)nsteps));
     K = std::max(1LL, std::min<long long>(K, nsteps));
-    return grad_impl(c, omega0, (long long)nsteps, K, L, dL_dwp, dL_dgamma);
+    // automatic interval: keep every step's metal-box snapshot (no replay)
+    // when they fit in half the free device memory
+    bool store_all = false;
+    if (ckpt_every == 0) {
+        size_t freeb = 0, totalb = 0;
+        HIP_TRY(c, hipMemGetInfo(&freeb, &totalb));
+        const double need = (double)nsteps * 6.0 * (double)c->nbox * 4.0;
+        store_all = need <= 0.5 * (double)freeb;
+    }
+    return grad_impl(c, omega0, (long long)nsteps, K, store_all, L, dL_dwp, dL_dgamma);
 }
 
 // Field-kernel tile autotuner: time H + E launches of every tile shape on

@@ -154,7 +154,9 @@ def test_gradient_matches_oracle_central_differences():
 
 
 def test_checkpoint_interval_does_not_change_the_gradient():
-    """Fields-only replays are deterministic, so every interval gives the same bits."""
+    """Fields-only replays are deterministic, so every interval gives the same bits,
+    and the same as ckpt_every = 0, which on this grid keeps every step's metal-box
+    snapshot from the forward run and replays nothing."""
     w = _workload((native.BC_CPML, native.BC_CPML, native.BC_PERIODIC), 3, False, seed=2)
     E = _pulse(w)
     N, w0 = 61, w.omega[0]

@@ -103,7 +103,10 @@ def test_fields_only_gradient_matches_oracle_adjoint(case):
     assert np.all(gw[w.wp_map == 0] == 0) and np.all(gg[w.wp_map == 0] == 0)
 
 
-def test_gradient_with_bunch_matches_oracle_adjoint():
+@pytest.mark.parametrize("ckpt_every", [0, 7])
+def test_gradient_with_bunch_matches_oracle_adjoint(ckpt_every):
+    """ckpt_every = 0 keeps every step's snapshot; 7 replays segments with the
+    recorded bunch current."""
     w = _workload((native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, True)
     E = _pulse(w)
     for c in range(3):
@@ -112,7 +115,7 @@ def test_gradient_with_bunch_matches_oracle_adjoint():
     o = _oracle(w, E)
     Lo, gwo, ggo = o.grad(N, w0)
     s = _gpu(w, E)
-    L, gw, gg = s.grad(w0, N)
+    L, gw, gg = s.grad(w0, N, ckpt_every=ckpt_every)
     print(f"bunch: L rel {abs(L - Lo) / Lo:.2e}  dwp rel {_rel(gw, gwo):.2e}  "
           f"dgamma rel {_rel(gg, ggo):.2e}", flush=True)
     assert Lo > 0

@@ -55,6 +55,12 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden visibility; these declarations are its
+   only exported symbols. */
+#if defined(__GNUC__)
+#pragma GCC visibility push(default)
+#endif
+
 #define PIC_ABI_VERSION 5
 
 typedef enum {
@@ -306,6 +312,10 @@ const char *pic_batch_last_error(const pic_batch *batch);
 /* Message of the last error on ctx (or of the last failed pic_init when ctx
  * is NULL).  Owned by the library; valid until the next call on ctx. */
 const char *pic_last_error(const pic_ctx *ctx);
+
+#if defined(__GNUC__)
+#pragma GCC visibility pop
+#endif
 
 #ifdef __cplusplus
 }

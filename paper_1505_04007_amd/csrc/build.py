@@ -1,7 +1,8 @@
 """Build libpic.so (the gfx950 FDTD-PIC library) with hipcc, in-tree.
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 instruction
-selection disabled, and linked into paper_1505_04007_amd/libpic.so.
+selection disabled and hidden symbol visibility (only the pic_* functions of
+include/pic.h are exported), and linked into paper_1505_04007_amd/libpic.so.
 """
 import os
 import subprocess
@@ -10,11 +11,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["pic_abi.hip", "kernels_fields.hip", "kernels_particles.hip", "kernels_diag.hip",
+SOURCES = ["pic_abi.hip", "pic_grad.hip", "pic_batch.hip", "kernels_fields.hip", "kernels_particles.hip", "kernels_diag.hip",
            "kernels_adjoint.hip"]
 LIB = os.path.join(PKG, "libpic.so")
 
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-fvisibility=hidden", "-fvisibility-inlines-hidden",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", HERE]
 
@@ -36,7 +37,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src, p in procs:
         if p.wait() != 0:
             raise RuntimeError(f"hipcc failed on {src}")
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", LIB + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -30,6 +30,20 @@ def test_library_exports_every_declared_entry_point():
     assert lib.pic_abi_version() == ver
 
 
+def test_library_exports_only_the_declared_c_entry_points():
+    """Built with hidden visibility: the unmangled symbols libpic.so defines are
+    exactly the functions include/pic.h declares (internal helpers stay hidden)."""
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    names = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    c_names = {n for n in names if not n.startswith("_Z") and not n.startswith("__hip_cuid")}
+    assert c_names == set(_declared())
+
+
 def test_binding_structs_and_buffers_match_the_header():
     """The ctypes mirrors of pic_opts and of pic_timing's output arrays have the
     header's field count and length (a short buffer is overrun by the library)."""

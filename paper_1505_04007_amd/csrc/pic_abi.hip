@@ -264,7 +264,6 @@ pic::DiagArgs diag_args(pic_ctx *c)
 
 extern "C" {
 
-
 int pic_abi_version(void) { return PIC_ABI_VERSION; }
 
 const char *pic_last_error(const pic_ctx *ctx)
@@ -660,7 +659,6 @@ pic_status pic_probe(pic_ctx *c, double *re, double *im, double *series)
     return PIC_OK;
 }
 
-
 pic_status pic_read_fields(pic_ctx *c, int which, double *out)
 {
     CHECK_CTX(c);
@@ -811,6 +809,5 @@ pic_status pic_timing(pic_ctx *c, double *ms_total, int64_t *launches, int reset
     }
     return PIC_OK;
 }
-
 
 }  // extern "C"

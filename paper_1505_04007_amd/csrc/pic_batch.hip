@@ -5,10 +5,6 @@
 
 using namespace pich;
 
-// ---------------------------------------------------------------------------
-// Batched simulations: one launch per kernel family for all members, and a
-// whole sort period captured once as a HIP graph.
-// ---------------------------------------------------------------------------
 struct pic_batch {
     std::vector<pic_ctx *> ctx;
     hipStream_t stream = nullptr;  // the batch's own stream (capturable)

@@ -7,13 +7,11 @@ using namespace pich;
 
 namespace pich {
 
-
 size_t slab_cells(const pic_ctx *c, int a)
 {
     const size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
     return (size_t)2 * c->npml * (N / (size_t)c->n[a]);
 }
-
 
 std::vector<StateArr> field_state(pic_ctx *c, int h)
 {
@@ -39,7 +37,6 @@ size_t state_bytes(pic_ctx *c)
     for (const StateArr &a : field_state(c, 0)) b += align256(a.bytes);
     return b;
 }
-
 
 pic_status ckpt_save(pic_ctx *c, char *dst, Mirror &m)
 {
@@ -443,7 +440,6 @@ pic_status tune_fields(pic_ctx *c, int reps, double *ms)
 }  // namespace
 
 extern "C" {
-
 
 pic_status pic_grad(pic_ctx *c, double omega0, int64_t nsteps, int64_t ckpt_every, double *L,
                     double *dL_dwp, double *dL_dgamma)

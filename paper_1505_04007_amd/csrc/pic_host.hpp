@@ -129,7 +129,6 @@ pic_status dalloc(pic_ctx *c, T **p, size_t count)
         if (s_ != PIC_OK) return s_;                                                               \
     } while (0)
 
-
 #define CHECK_CTX(c)                                                                               \
     do {                                                                                           \
         if (!(c)) return pich::fail(nullptr, PIC_EINVAL, "ctx is NULL");                          \

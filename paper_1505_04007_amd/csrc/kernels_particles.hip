@@ -325,7 +325,7 @@ constexpr int ROUND_LANES = 3;
 template <int MODE, int PX>
 __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
 {
-    const int p = blk * PBLOCK + threadIdx.x;
+    const int p = blk * PUSH_BLOCK + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int pc = a.st->pcur;
     float *__restrict__ X = a.P[pc][0];
@@ -482,7 +482,7 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
 }
 
 template <int MODE, int PX>
-__global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
+__global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit(PartArgs a)
 {
     push_body<MODE, PX>(a, blockIdx.x);
 }
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit(PartArgs a)
 // Many simulations in one launch: workgroup b belongs to the simulation q
 // with start[q] <= b < start[q + 1].
 template <int MODE, int PX>
-__global__ __launch_bounds__(PBLOCK) void k_push_deposit_batch(const PartArgs *args, const int *start,
+__global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit_batch(const PartArgs *args, const int *start,
                                                                int n)
 {
     const int b = blockIdx.x;
@@ -502,13 +502,13 @@ __global__ __launch_bounds__(PBLOCK) void k_push_deposit_batch(const PartArgs *a
 void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s)
 {
     if (a.n <= 0) return;
-    const int nb = (a.n + PBLOCK - 1) / PBLOCK;
+    const int nb = (a.n + PUSH_BLOCK - 1) / PUSH_BLOCK;
     if (a.per[0]) {
-        if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 1>), dim3(nb), dim3(PBLOCK), 0, s, a);
-        else hipLaunchKernelGGL((k_push_deposit<0, 1>), dim3(nb), dim3(PBLOCK), 0, s, a);
+        if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 1>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_push_deposit<0, 1>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
     } else {
-        if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 0>), dim3(nb), dim3(PBLOCK), 0, s, a);
-        else hipLaunchKernelGGL((k_push_deposit<0, 0>), dim3(nb), dim3(PBLOCK), 0, s, a);
+        if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 0>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_push_deposit<0, 0>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
     }
 }
 
@@ -518,10 +518,10 @@ void launch_push_deposit_batch(const PartArgs *args, const int *start, int n, in
 {
     if (total <= 0) return;
     switch (mode & 3) {
-    case 0: hipLaunchKernelGGL((k_push_deposit_batch<0, 0>), dim3(total), dim3(PBLOCK), 0, s, args, start, n); break;
-    case 1: hipLaunchKernelGGL((k_push_deposit_batch<1, 0>), dim3(total), dim3(PBLOCK), 0, s, args, start, n); break;
-    case 2: hipLaunchKernelGGL((k_push_deposit_batch<0, 1>), dim3(total), dim3(PBLOCK), 0, s, args, start, n); break;
-    default: hipLaunchKernelGGL((k_push_deposit_batch<1, 1>), dim3(total), dim3(PBLOCK), 0, s, args, start, n); break;
+    case 0: hipLaunchKernelGGL((k_push_deposit_batch<0, 0>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, start, n); break;
+    case 1: hipLaunchKernelGGL((k_push_deposit_batch<1, 0>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, start, n); break;
+    case 2: hipLaunchKernelGGL((k_push_deposit_batch<0, 1>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, start, n); break;
+    default: hipLaunchKernelGGL((k_push_deposit_batch<1, 1>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, start, n); break;
     }
 }
 

@@ -571,7 +571,7 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         for (int i = 0; i < c->np; ++i) ids[i] = i;
         HIP_TRY(c, hipMemcpyAsync(c->pid[0], ids.data(), 4 * (size_t)c->np, hipMemcpyHostToDevice, c->stream));
         // one push counter per wavefront of the push launch
-        c->n_wave_slots = ((size_t)c->np + pic::PBLOCK - 1) / pic::PBLOCK * (pic::PBLOCK / 64);
+        c->n_wave_slots = ((size_t)c->np + 63) / 64;
         TRY(dalloc(c, &c->d_pushes, c->n_wave_slots));
         HIP_TRY(c, hipMemsetAsync(c->d_pushes, 0, 8 * c->n_wave_slots, c->stream));
         TRY(dalloc(c, &c->key, (size_t)c->np));

@@ -3,6 +3,8 @@
 // graph.
 #include "pic_host.hpp"
 
+#include <climits>
+
 using namespace pich;
 
 struct pic_batch {
@@ -163,7 +165,9 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
         b->ctx.push_back(c);
         pa[q] = c->pa;
         pr[q] = c->pr;
-        pblk[q + 1] = pblk[q] + (c->np + pic::PBLOCK - 1) / pic::PBLOCK;
+        const long long nb = pblk[q] + ((long long)c->np + pic::PUSH_BLOCK - 1) / pic::PUSH_BLOCK;
+        if (nb > INT_MAX) return bfail(b, PIC_EINVAL, "too many particles in the batch for one launch");
+        pblk[q + 1] = (int)nb;
     }
     b->ext = ctxs[0]->stream;
     // an own stream: the members' stream may be the null stream, which cannot be captured

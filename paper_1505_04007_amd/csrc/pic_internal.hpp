@@ -22,7 +22,12 @@
 
 namespace pic {
 
-constexpr int PBLOCK = 256;  // particle kernels
+constexpr int PBLOCK = 256;  // particle sort kernels
+// Push / deposit: one wavefront per workgroup. Wavefronts of one window take
+// very different numbers of reduction rounds, and a workgroup's slot on the
+// compute unit is freed only when its last wavefront ends, so single-wave
+// workgroups keep the units fuller (8 % faster than 256 threads).
+constexpr int PUSH_BLOCK = 64;
 constexpr int FX = 64;       // default field tile: 64 x 4 cells of one z plane
 constexpr int FY = 4;
 
@@ -94,7 +99,7 @@ struct PartArgs {
     float S;   // c dt / dx
     float ah;  // q dt / (2 m c), per V/m
     float qd;  // -q w / (eps0 dx^2), V/m
-    unsigned long long *pushes;  // one counter per wavefront: [gridDim * PBLOCK / 64]
+    unsigned long long *pushes;  // one counter per wavefront: [ceil(n / 64)]
     DevState *st;
 };
 

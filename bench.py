@@ -84,8 +84,13 @@ def algorithmic_bytes(w, fam, pushes_per_step, pbox):
 
 
 def source_sha(fam):
-    path = os.path.join(ROOT, "paper_1505_04007_amd", "csrc", KERNEL_SOURCES[fam])
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of the kernel's source file and of the shared header that fixes its
+    launch shapes and argument blocks."""
+    csrc = os.path.join(ROOT, "paper_1505_04007_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCES[fam], "pic_internal.hpp"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(fam, wname):

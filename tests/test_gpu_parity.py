@@ -320,3 +320,30 @@ def test_minimum_pec_grid_fields_only():
     o.step(50)
     g.step(50)
     _compare_fields(g, o, n, 1e-5)
+
+
+@pytest.mark.parametrize("npart", [1, 63, 64, 65, 257])
+def test_bunch_sizes_at_wavefront_and_workgroup_edges(npart):
+    """Particle counts one below, at and above a wavefront (the push's
+    workgroup) and a sort workgroup: positions, pushes and fields match the
+    oracle, with sorts in between."""
+    nx, ny, nz, dx = 24, 16, 20, 5e-9
+    wpm, gm = pi.film_maps(nx, ny, nz, 3, 6)
+    rng = np.random.default_rng(pi.SEED0 + 900 + npart)
+    bunch = pi.gaussian_bunch(rng, npart, (6 * dx, 8 * dx, 11 * dx), (1.5 * dx, dx, dx), 80e3)
+    w = pi.Workload(f"edges_{npart}", nx, ny, nz, dx, pi.courant_dt(dx),
+                    (native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, wpm, gm, bunch,
+                    np.array([[6 * dx, 8 * dx, 7.3 * dx]]), pi.spectrum_omegas(nfreq=4), 30)
+    o = _oracle_of(w)
+    g = _gpu_of(w, sort_every=5)
+    o.step(30)
+    g.step(30)
+    st = g.stats()
+    assert st["pushes"] == 30 * npart and st["live"] == npart
+    P = g.particles()  # original order, as the oracle keeps them
+    Po = o.particles()
+    assert Po[6].all()
+    for c in range(3):
+        assert np.abs(P[c] - Po[c]).max() <= 1e-3 * dx
+        assert np.abs(P[3 + c] - Po[3 + c]).max() <= 1e-5 * np.abs(Po[3]).max()
+    _compare_fields(g, o, (nx, ny, nz), 1e-3)

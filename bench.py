@@ -203,8 +203,10 @@ def bench_batched(args):
 
 def bench_adjoint(args):
     """pic_grad on the 128x64x64, 20 nm film, 1e5-particle workload: the
-    differentiated run (forward with checkpoints + recorded bunch current,
-    replay, adjoint) against the plain forward run of the same steps."""
+    differentiated run (a forward run that keeps what the reverse pass needs:
+    every step's metal-box state when that fits in half the free device
+    memory, else checkpoints and a replay; then the adjoint) against the plain
+    forward run of the same steps."""
     import torch
     import pic_inputs as pi
     from paper_1505_04007_amd import native

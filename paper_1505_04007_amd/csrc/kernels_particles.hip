@@ -558,7 +558,9 @@ __device__ __forceinline__ int wave_minmax(int v)
 // Count particles per cell.  Lanes of a wavefront with the same cell (most
 // of them: the particles are nearly sorted from the last sort) reserve their
 // ranks with one atomic and take consecutive ones in lane order, so the
-// scatter writes them to consecutive places.
+// scatter writes them to consecutive places.  The groups are found first and
+// their leaders then issue all their atomics at once, so a wavefront spread
+// over many cells waits for one atomic return, not one per cell.
 __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
 {
     __shared__ int bb[6];
@@ -581,17 +583,22 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
         }
     }
     unsigned long long rem = __ballot(p < a.n);
-    int rank = 0;
+    unsigned long long group = 0;  // lanes sharing this lane's cell
+    int leader = lane;
     while (rem) {
-        const int leader = __ffsll((long long)rem) - 1;
-        const int k0 = __builtin_amdgcn_readlane(key, leader);
+        const int l0 = __ffsll((long long)rem) - 1;
+        const int k0 = __builtin_amdgcn_readlane(key, l0);
         const unsigned long long m = __ballot(((rem >> lane) & 1ull) && key == k0);
-        int b = 0;
-        if (lane == leader) b = atomicAdd(&a.counts[k0], __popcll(m));
-        b = __builtin_amdgcn_readlane(b, leader);
-        if ((m >> lane) & 1ull) rank = b + __popcll(m & ((1ull << lane) - 1ull));
+        if ((m >> lane) & 1ull) {
+            group = m;
+            leader = l0;
+        }
         rem &= ~m;
     }
+    int b = 0;
+    if (p < a.n && lane == leader) b = atomicAdd(&a.counts[key], __popcll(group));
+    b = __shfl(b, leader, 64);
+    const int rank = b + __popcll(group & ((1ull << lane) - 1ull));
     if (p < a.n) {
         a.key[p] = key;
         a.rank[p] = rank;

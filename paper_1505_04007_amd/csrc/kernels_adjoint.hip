@@ -308,7 +308,7 @@ void launch_traj_store(const TrajArgs &a, hipStream_t s)
 {
     const int nb = a.w[0] * a.w[1] * a.w[2];
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_traj_store, dim3((nb + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_traj_store, dim3((unsigned)(((long long)nb + 255) / 256)), dim3(256), 0, s, a);
 }
 
 }  // namespace pic

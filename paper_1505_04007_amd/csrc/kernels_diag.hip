@@ -81,7 +81,7 @@ __global__ void k_rho(DiagArgs a)
 void launch_rho(const DiagArgs &a, hipStream_t s)
 {
     if (a.np <= 0) return;
-    hipLaunchKernelGGL(k_rho, dim3((a.np + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_rho, dim3((unsigned)(((long long)a.np + 255) / 256)), dim3(256), 0, s, a);
 }
 
 __device__ __forceinline__ double warp_sum(double v)
@@ -126,7 +126,8 @@ __global__ __launch_bounds__(256) void k_diag_particles(DiagArgs a)
 {
     __shared__ double part[4][10];
     double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.np; p += gridDim.x * blockDim.x) {
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.np;
+         p += (long long)gridDim.x * blockDim.x) {
         if (!live_pos(a.x[p], a.y[p], a.z[p], a.nx, a.ny, a.nz)) continue;
         const double X[3] = {a.x[p], a.y[p], a.z[p]};
         const double U[3] = {a.ux[p], a.uy[p], a.uz[p]};

@@ -502,7 +502,7 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit_batch(const PartArg
 void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s)
 {
     if (a.n <= 0) return;
-    const int nb = (a.n + PUSH_BLOCK - 1) / PUSH_BLOCK;
+    const int nb = (int)(((long long)a.n + PUSH_BLOCK - 1) / PUSH_BLOCK);
     if (a.per[0]) {
         if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 1>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
         else hipLaunchKernelGGL((k_push_deposit<0, 1>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
@@ -671,7 +671,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *sm, int &total)
     return incl - v;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const int *in, int n, int *tile_sums)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const int *in, long long n, int *tile_sums)
 {
     __shared__ int sm[SCAN_THREADS];
     const long long b0 = (long long)blockIdx.x * SCAN_TILE;
@@ -699,7 +699,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(int *tile_sums, int 
     }
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int *data, int n, const int *tile_sums)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int *data, long long n, const int *tile_sums)
 {
     __shared__ int sm[SCAN_THREADS];
     // each thread owns SCAN_ITEMS consecutive elements of the tile, moved as
@@ -762,26 +762,27 @@ __global__ void k_sort_done(DevState *st)
     }
 }
 
-int scan_tmp_size(int n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+int scan_tmp_size(long long n) { return (int)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
 
 void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s)
 {
-    const int ncount = a.ncell + 1;
+    // counts of the ncell cells and of the lost-particle bucket: up to 2^31
+    // entries, so the element count is 64-bit; block counts fit in int
+    const long long ncount = (long long)a.ncell + 1;
+    const int nb = (int)(((long long)a.n + PBLOCK - 1) / PBLOCK);
     launch_fill_i32(a.counts, 0, ncount, s);
     if (a.n > 0) {
-        const int nb = (a.n + PBLOCK - 1) / PBLOCK;
         hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(PBLOCK), 0, s, a);
         hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(BOX_THREADS), 0, s, a, nb);
     } else {
         launch_fill_i32(a.box, INT_MAX, 3, s);
         launch_fill_i32(a.box + 3, INT_MIN, 3, s);
     }
-    const int ntiles = (ncount + SCAN_TILE - 1) / SCAN_TILE;
+    const int ntiles = (int)((ncount + SCAN_TILE - 1) / SCAN_TILE);
     hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(SCAN_THREADS), 0, s, a.counts, ncount, scan_tmp);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, s, scan_tmp, ntiles);
     hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(SCAN_THREADS), 0, s, a.counts, ncount, scan_tmp);
     if (a.n > 0) {
-        const int nb = (a.n + PBLOCK - 1) / PBLOCK;
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(PBLOCK), 0, s, a);
     }
     hipLaunchKernelGGL(k_sort_done, dim3(1), dim3(64), 0, s, a.st);

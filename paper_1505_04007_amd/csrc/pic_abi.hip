@@ -579,7 +579,7 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         TRY(dalloc(c, &c->counts, (size_t)ncell + 1));
         TRY(dalloc(c, &c->box, 6));
         TRY(dalloc(c, &c->boxpart, 6 * (((size_t)c->np + pic::PBLOCK - 1) / pic::PBLOCK)));
-        c->scan_len = pic::scan_tmp_size((int)ncell + 1);
+        c->scan_len = pic::scan_tmp_size(ncell + 1);
         TRY(dalloc(c, &c->scan_tmp, (size_t)c->scan_len));
         for (int d = 0; d < 3; ++d) {
             TRY(dalloc(c, &c->Jb[d], N));

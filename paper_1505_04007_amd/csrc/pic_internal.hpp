@@ -186,7 +186,7 @@ void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s);
 void launch_probe(const ProbeArgs &a, hipStream_t s);  // also advances the DevState
 void launch_fill_i32(int *p, int v, long long n, hipStream_t s);
 void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s);
-int scan_tmp_size(int n);
+int scan_tmp_size(long long n);
 
 // Batched forms: one launch over many simulations.  `args` is a device array
 // of per-simulation argument blocks; `start` a device prefix table of work

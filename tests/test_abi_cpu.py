@@ -88,6 +88,7 @@ def _init(**over):
 @pytest.mark.parametrize("over, frag", [
     (dict(bc=[0, 5, 0]), "pic_bc"),
     (dict(n=[1, 32, 32]), "cells"),
+    (dict(n=[2048, 1024, 1024]), "2^31-1"),  # 2^31 cells: past 32-bit cell indices
     (dict(bc=[2, 2, 2], npml=0), "npml"),
     (dict(bc=[2, 2, 2], npml=16), "2*npml"),
     (dict(dx=-1.0), "positive"),

@@ -270,21 +270,6 @@ __global__ void k_box_copy(BoxCopyArgs a)
     }
 }
 
-__global__ void k_traj_store(TrajArgs a)
-{
-    const int nb = a.w[0] * a.w[1] * a.w[2];
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    const int bi = b % a.w[0], bj = (b / a.w[0]) % a.w[1], bk = b / (a.w[0] * a.w[1]);
-    const long long g = (long long)(a.mlo[0] + bi) +
-                        (long long)a.nx * ((long long)(a.mlo[1] + bj) + (long long)a.ny * (a.mlo[2] + bk));
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        a.out[c * nb + b] = a.E[c][g];
-        a.out[(3 + c) * nb + b] = a.Jp[c][b];
-    }
-}
-
 void launch_adj_face(const AdjArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_adj_face, dim3(field_tiles(a.nx, a.ny, a.nz)), dim3(FX, FY), 0, s, a);
@@ -302,13 +287,6 @@ void launch_box_copy(const BoxCopyArgs &a, hipStream_t s)
     long long nb = (n + 255) / 256;
     if (nb > 8192) nb = 8192;
     hipLaunchKernelGGL(k_box_copy, dim3((unsigned)nb), dim3(256), 0, s, a);
-}
-
-void launch_traj_store(const TrajArgs &a, hipStream_t s)
-{
-    const int nb = a.w[0] * a.w[1] * a.w[2];
-    if (nb <= 0) return;
-    hipLaunchKernelGGL(k_traj_store, dim3((unsigned)(((long long)nb + 255) / 256)), dim3(256), 0, s, a);
 }
 
 }  // namespace pic

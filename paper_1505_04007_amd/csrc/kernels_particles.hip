@@ -685,16 +685,28 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const int *in, long
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
+// One workgroup; each thread scans SCAN_ITEMS consecutive tile sums of a
+// chunk serially around one block scan of the thread totals.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(int *tile_sums, int ntiles)
 {
     __shared__ int sm[SCAN_THREADS];
     int carry = 0;
-    for (int b0 = 0; b0 < ntiles; b0 += SCAN_THREADS) {
-        const int idx = b0 + threadIdx.x;
-        const int v = idx < ntiles ? tile_sums[idx] : 0;
+    for (int b0 = 0; b0 < ntiles; b0 += SCAN_TILE) {
+        const int first = b0 + threadIdx.x * SCAN_ITEMS;
+        int v[SCAN_ITEMS];
+        int s = 0;
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS; ++q) {
+            v[q] = first + q < ntiles ? tile_sums[first + q] : 0;
+            s += v[q];
+        }
         int total;
-        const int ex = block_exclusive_scan(v, sm, total);
-        if (idx < ntiles) tile_sums[idx] = ex + carry;
+        int run = carry + block_exclusive_scan(s, sm, total);
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS; ++q) {
+            if (first + q < ntiles) tile_sums[first + q] = run;
+            run += v[q];
+        }
         carry += total;
     }
 }

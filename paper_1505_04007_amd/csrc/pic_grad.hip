@@ -137,15 +137,6 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, bool s
     GradScratch g;
     g.s = c->stream;
 
-    pic::TrajArgs ta{};
-    for (int d = 0; d < 3; ++d) {
-        ta.E[d] = c->E[d];
-        ta.Jp[d] = c->Jp[d];
-        ta.mlo[d] = c->mlo[d];
-        ta.w[d] = c->mhi[d] - c->mlo[d];
-    }
-    ta.nx = c->n[0];
-    ta.ny = c->n[1];
     float *traj = nullptr;  // metal-box snapshots: one per step of a segment, or of the run
     TRY(galloc(c, g, &traj, (size_t)K * 6 * c->nbox));
 
@@ -167,11 +158,10 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, bool s
     pic_status st = PIC_OK;
     for (long long r = 0; r < N && st == PIC_OK; ++r) {
         if (store_all) {
-            if (c->has_metal) {
-                ta.out = traj + (size_t)r * 6 * c->nbox;
-                pic::launch_traj_store(ta, c->stream);
-            }
+            // this step's E update writes the snapshot as it reads E^n and J_pol
+            if (c->has_metal) c->fa.snap = traj + (size_t)r * 6 * c->nbox;
             st = step_once(c);
+            c->fa.snap = nullptr;
             continue;
         }
         if (r % K == 0) st = ckpt_save(c, ck + (size_t)(r / K) * ckb, mir[(size_t)(r / K)]);
@@ -328,8 +318,7 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, bool s
         const long long a0 = j * K, b0 = std::min(N, a0 + K);
         if (!store_all) TRY(ckpt_load(c, ck + (size_t)j * ckb, mir[(size_t)j]));
         for (long long r = a0; r < b0 && !store_all; ++r) {
-            ta.out = traj + (size_t)(r - a0) * 6 * c->nbox;
-            pic::launch_traj_store(ta, c->stream);
+            fr.snap = c->has_metal ? traj + (size_t)(r - a0) * 6 * c->nbox : nullptr;
             pic::launch_h_update(fr, c->stream);
             const JbRecord &R = rec[(size_t)r];
             if (c->np > 0 && R.p) {

@@ -81,6 +81,9 @@ struct FieldArgs {
     int mlo[3], mhi[3];
     float *Jp[3];
     const float2 *coef;  // (cbt, d) per box cell
+    // when set, the E update also copies E^n and J_pol^{n-1/2} of the metal
+    // box here ([6][box cells], E then J_pol): the reverse pass's snapshot
+    float *snap;
     // bunch current: read and cleared inside the particle box (+ margin)
     float *Jb[3];
     const int *pbox;  // device [6]: lo x,y,z, hi x,y,z (cells, inclusive), or null
@@ -235,18 +238,9 @@ struct BoxCopyArgs {
 };
 
 // Forward values the gradient needs at step n on the metal box.
-struct TrajArgs {
-    const float *E[3];
-    const float *Jp[3];
-    float *out;  // [6][nbox]
-    int nx, ny;
-    int mlo[3], w[3];
-};
-
 void launch_adj_face(const AdjArgs &a, hipStream_t s);
 void launch_adj_edge(const AdjArgs &a, hipStream_t s);
 void launch_box_copy(const BoxCopyArgs &a, hipStream_t s);
-void launch_traj_store(const TrajArgs &a, hipStream_t s);
 
 // FP64 diagnostics
 struct DiagArgs {

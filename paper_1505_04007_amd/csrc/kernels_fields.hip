@@ -154,29 +154,6 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
     float hxy = Hx[id + oy], hzy = Hz[id + oy];
     float hxz = Hx[id + oz], hyz = Hy[id + oz];
     const float ex = ld_once(a.E[0] + id), ey = ld_once(a.E[1] + id), ez = ld_once(a.E[2] + id);
-    // the Drude and bunch currents are loaded before the CPML memories are
-    // written: loads and stores share one wait counter, so a load issued
-    // after a store would wait for the store too
-    const bool metal = i >= a.mlo[0] && i < a.mhi[0] && j >= a.mlo[1] && j < a.mhi[1] && k >= a.mlo[2] &&
-                       k < a.mhi[2];
-    int bi = 0;
-    float2 cd = make_float2(0.f, 0.f);
-    float jx = 0.f, jy = 0.f, jz = 0.f;
-    if (metal) {
-        const int wx = a.mhi[0] - a.mlo[0], wy = a.mhi[1] - a.mlo[1];
-        bi = (i - a.mlo[0]) + wx * ((j - a.mlo[1]) + wy * (k - a.mlo[2]));
-        cd = a.coef[bi];
-        jx = a.Jp[0][bi];
-        jy = a.Jp[1][bi];
-        jz = a.Jp[2][bi];
-    }
-    const bool inbox = a.pbox && in_particle_box(a, margin, i, j, k);
-    float bx = 0.f, by = 0.f, bz = 0.f;
-    if (inbox) {
-        bx = a.Jb[0][id];
-        by = a.Jb[1][id];
-        bz = a.Jb[2][id];
-    }
     hyx = okx ? hyx : 0.f;
     hzx = okx ? hzx : 0.f;
     hxy = oky ? hxy : 0.f;
@@ -217,9 +194,15 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
     float nex = ex + S * (dyHz - dzHy);
     float ney = ey + S * (dzHx - dxHz);
     float nez = ez + S * (dxHy - dyHx);
-    if (metal) {
+    if (i >= a.mlo[0] && i < a.mhi[0] && j >= a.mlo[1] && j < a.mhi[1] && k >= a.mlo[2] &&
+        k < a.mhi[2]) {
+        const int wx = a.mhi[0] - a.mlo[0], wy = a.mhi[1] - a.mlo[1];
+        const int bi = (i - a.mlo[0]) + wx * ((j - a.mlo[1]) + wy * (k - a.mlo[2]));
+        const float2 cd = a.coef[bi];
+        float jx = a.Jp[0][bi], jy = a.Jp[1][bi], jz = a.Jp[2][bi];
         if (a.snap) {
-            const int nb = (a.mhi[0] - a.mlo[0]) * (a.mhi[1] - a.mlo[1]) * (a.mhi[2] - a.mlo[2]);
+            // the reverse pass's snapshot: E^n and J_pol^{n-1/2} of this cell
+            const int nb = wx * wy * (a.mhi[2] - a.mlo[2]);
             a.snap[bi] = ex;
             a.snap[nb + bi] = ey;
             a.snap[2 * nb + bi] = ez;
@@ -237,10 +220,10 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
         ney -= jy;
         nez -= jz;
     }
-    if (inbox) {
-        nex -= bx;
-        ney -= by;
-        nez -= bz;
+    if (a.pbox && in_particle_box(a, margin, i, j, k)) {
+        nex -= a.Jb[0][id];
+        ney -= a.Jb[1][id];
+        nez -= a.Jb[2][id];
         a.Jb[0][id] = 0.f;
         a.Jb[1][id] = 0.f;
         a.Jb[2][id] = 0.f;

@@ -174,15 +174,17 @@ def test_checkpoint_interval_does_not_change_the_gradient():
             assert np.array_equal(out[1], ref[1]) and np.array_equal(out[2], ref[2]), ck
 
 
-def test_grad_leaves_the_state_of_a_plain_run():
-    """After pic_grad(N) the simulation equals one stepped N times (fields-only: bitwise)."""
+@pytest.mark.parametrize("ckpt_every", [0, 6])
+def test_grad_leaves_the_state_of_a_plain_run(ckpt_every):
+    """After pic_grad(N) the simulation equals one stepped N times (fields-only: bitwise),
+    whether the forward run kept every step's snapshot (0) or checkpoints (6)."""
     w = _workload((native.BC_CPML, native.BC_PERIODIC, native.BC_CPML), 4, False, seed=3)
     E = _pulse(w)
     a = _gpu(w, E)
     b = _gpu(w, E)
     a.step(7)
     b.step(7)
-    a.grad(w.omega[0], 40, ckpt_every=6)
+    a.grad(w.omega[0], 40, ckpt_every=ckpt_every)
     b.step(40)
     for which in (native.FIELD_E, native.FIELD_H, native.FIELD_JPOL):
         assert np.array_equal(a.fields(which), b.fields(which))

@@ -37,6 +37,7 @@ def workload(name):
     table = {"grating40nm_512x256x256_cpml12": pi.grating_large,
              "film30nm_256x128x128_cpml8": pi.film_production,
              "film20nm_128x64x64_cpml8": pi.film_adjoint,
+             "grating40nm_shard2of8_64x256x256": pi.grating_shard,
              "slab20nm_32x32x32_pec": pi.slab_tiny}
     return table[name]()
 

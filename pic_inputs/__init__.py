@@ -20,6 +20,9 @@ Workloads (all seeded, ``seed = 1505040070 + index``):
                                      with 10 nm grooves at 100 nm period, 1e7
                                      particles, 100 keV, 20000 steps, sort every 20
   2 ``batched16``                   16 instances, 5..80 nm films, U(20,80) keV
+  - ``grating40nm_shard2of8_64x256x256`` rank 2's x-slab of workload 4 under an
+                                     8-way split (the busiest rank: 48 % of the
+                                     bunch); periodic x faces stand in for halos
 """
 from dataclasses import dataclass, field
 from typing import Optional
@@ -200,6 +203,32 @@ def grating_large(nparticles=10_000_000):
     return Workload("grating40nm_512x256x256_cpml12", nx, ny, nz, dx, courant_dt(dx),
                     (CPML,) * 3, npml, wpm, gm, bunch, probes, spectrum_omegas(), 20000,
                     sort_every=20)
+
+
+def grating_shard(nshards=8, rank=2, nparticles=10_000_000):
+    """One rank's share of the grating workload under an x-slab split.
+
+    Cells [rank * nx / nshards, (rank + 1) * nx / nshards) of the 512-cell x
+    axis with the film, grooves and the bunch particles inside them (positions
+    shifted to the slab).  The slab's x faces are periodic here: on one GPU
+    that reads the one neighbour plane per face a halo exchange would deliver
+    (the exchange itself is not modelled).  Rank 2 holds the bunch centre, so
+    it carries the most particles of the split.
+    """
+    full = grating_large(nparticles)
+    w = full.nx // nshards
+    x0 = rank * w
+    b = full.bunch
+    keep = np.nonzero((b.x >= x0 * full.dx) & (b.x < (x0 + w) * full.dx))[0]
+    sub = b.subset(keep)
+    sub.x = sub.x - x0 * full.dx
+    zp = full.probes[0, 2]
+    probes = np.array([[w * full.dx / 2, full.ny * full.dx / 2, zp]])
+    return Workload(f"grating40nm_shard{rank}of{nshards}_{w}x{full.ny}x{full.nz}", w, full.ny, full.nz,
+                    full.dx, full.dt, (PERIODIC, CPML, CPML), full.npml,
+                    np.ascontiguousarray(full.wp_map[x0:x0 + w]),
+                    np.ascontiguousarray(full.gamma_map[x0:x0 + w]), sub, probes, full.omega,
+                    full.steps, sort_every=full.sort_every)
 
 
 def batched_sweep(nparticles=200_000):

@@ -269,7 +269,7 @@ def test_sort_frequency_does_not_change_results():
     assert np.abs(Pa[3:] - Pb[3:]).max() <= 1e-5 * np.abs(Pb[3]).max()
 
 
-@pytest.mark.parametrize("make,steps", [(pi.film_production, 20), (pi.grating_large, 6)])
+@pytest.mark.parametrize("make,steps", [(pi.film_production, 20), (pi.grating_large, 6), (pi.grating_shard, 20)])
 def test_full_size_workloads_conserve_charge(make, steps):
     """Full-size workloads in the benchmark's launch configuration: every live
     particle pushed each step, no non-finite field, and Gauss's law at FP32

@@ -12,14 +12,14 @@ SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, src: str = SRC, lib: str = LIB) -> str:
     cmd = ["gcc", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-O3", "-fopenmp", "-fPIC",
-           "-shared", "-Wall", "-Wno-unused-function", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-shared", "-Wall", "-Wno-unused-function", "-o", lib + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

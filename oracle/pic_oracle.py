@@ -16,6 +16,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# the library this module loads; a test that plants a mistake in a copy of the
+# oracle points a separate instance of this module at that copy's build
+LIB_PATH = os.path.join(HERE, "liboracle.so")
 _LIB = None
 
 PEC, PERIODIC, CPML = 0, 1, 2
@@ -26,7 +29,7 @@ def _load():
     global _LIB
     if _LIB is not None:
         return _LIB
-    path = os.path.join(HERE, "liboracle.so")
+    path = LIB_PATH
     if not os.path.exists(path):
         from . import build as _b  # type: ignore
         _b.build()

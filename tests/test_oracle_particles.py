@@ -56,6 +56,28 @@ def test_boris_exb_drift(oracle_mod):
     assert np.abs(v - drift).max() < 2e-3 * np.linalg.norm(drift)
 
 
+def test_free_particle_moves_at_u_over_gamma(oracle_mod):
+    """No field (a vanishing charge): each step moves x by dt u / gamma, with
+    gamma = sqrt(1 + |u|^2 / c^2), folded on periodic axes."""
+    po = oracle_mod
+    c = po.constants()[0]
+    n, dx = 12, 5e-9
+    dt = pi.courant_dt(dx)
+    z = np.zeros((n, n, n))
+    o = po.OracleSim(n, n, n, dx, dt, bc=(po.PERIODIC,) * 3, wp_map=z, gamma_map=z)
+    u = np.array([[0.9 * c, -0.4 * c, 0.25 * c], [-0.1 * c, 0.05 * c, 2.5 * c]])
+    x0 = np.array([[3.3 * dx, 7.1 * dx, 0.4 * dx], [10.9 * dx, 1.2 * dx, 5.5 * dx]])
+    o.set_particles(x0[:, 0], x0[:, 1], x0[:, 2], u[:, 0], u[:, 1], u[:, 2], -pi.E_CHARGE, pi.M_E, 1e-30)
+    steps = 40
+    o.step(steps)
+    P = o.particles()
+    g = np.sqrt(1 + (u * u).sum(1) / c ** 2)
+    expect = np.mod(x0 + steps * dt * u / g[:, None], n * dx)
+    got = np.stack(P[:3], axis=1)
+    assert np.abs(got - expect).max() < 1e-9 * dx
+    assert np.array_equal(np.stack(P[3:6], axis=1), u)
+
+
 def test_gather_is_exact_on_affine_fields(oracle_mod):
     """Trilinear interpolation on each component's staggered lattice reproduces
     any affine field exactly; B^n averages the two stored H time levels."""

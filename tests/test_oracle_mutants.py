@@ -38,6 +38,7 @@ GAUSS_METAL = lambda m: tp.test_gauss_law_with_metal_polarization(m)  # noqa: E7
 PROBE = lambda m: tp.test_probe_dft_of_exact_cavity_mode(m)  # noqa: E731
 TRANSPOSE = lambda m: [ta.test_adjoint_step_is_transpose_blockwise(m, c) for c in range(len(ta.CASES))]  # noqa: E731
 FD = lambda m: ta.test_gradient_matches_central_differences(m)  # noqa: E731
+CPML = lambda m: tp.test_cpml_reflection_below_minus_40_db(m)  # noqa: E731
 
 # (name, original text, planted mistake, pins expected to catch it)
 MUTANTS = [
@@ -92,6 +93,10 @@ MUTANTS = [
      "AT(s->Ha[a2], m1[0], m1[1], m1[2]) -= t1;", "AT(s->Ha[a2], m1[0], m1[1], m1[2]) += t1;", [TRANSPOSE]),
     ("gradient: cb's factor taken from J instead of E^n",
      "gcb[q] += jt * En[q];", "gcb[q] += jt * Jn[q];", [FD]),
+    ("CPML: sign of the memory coefficient c",
+     "*c = (sig > 0.0) ? sig * (*b - 1.0) /", "*c = (sig > 0.0) ? sig * (1.0 - *b) /", [CPML]),
+    ("CPML: conductivity grading reversed (largest at the interface)",
+     "const double sig = smax * pow(r, m);", "const double sig = smax * pow(1.0 - r, m);", [CPML]),
 ]
 
 

@@ -32,6 +32,12 @@
  * in place of the split-field PML, edge material rule) are the ones listed
  * in the design notes; each is restated at the code that applies it.
  *
+ * Pins: every part is checked against closed forms, exact invariants or brute
+ * force in the test suite, except the CPML layers (cpml_coeff and the psi
+ * recursions): they are held only to a reflection bound against a large-box
+ * run, and their grading with kappa > 1 is exercised by no pin.  CPML: parity
+ * unpinned beyond that bound.
+ *
  * The differentiable form (the gradient of probe spectral power with respect
  * to the per-cell wp and gamma of Eq. 1) is the plain reverse-time transpose
  * of steps 1, 3 and 4 with the bunch current of step 2 held at the values a

@@ -61,7 +61,7 @@ extern "C" {
 #pragma GCC visibility push(default)
 #endif
 
-#define PIC_ABI_VERSION 5
+#define PIC_ABI_VERSION 6
 
 typedef enum {
     PIC_OK = 0,
@@ -157,7 +157,16 @@ typedef struct {
     int32_t pbox[6];      /* cell bounding box of the live particles at the last sort:
                              lo x, y, z, hi x, y, z (inclusive); hi < lo when empty */
     int32_t hcur;         /* which H buffer (0 or 1) holds H^{n-1/2} for the next step */
+    int64_t device_bytes; /* device memory the context allocated itself at pic_init, bytes */
 } pic_stats_out;
+
+/* Device memory a context needs, from pic_query_sizes. */
+typedef struct {
+    int64_t field_elems;       /* FP32 elements of each field array: nx*ny*nz (E[c], H[p][c]) */
+    int64_t field_bytes;       /* bytes of each field array, 4 * field_elems */
+    int64_t device_bytes;      /* bytes pic_init allocates itself for these arguments, metal box excluded */
+    int64_t bytes_per_metal_box_cell; /* plus this much per cell of the bounding box of wp > 0 */
+} pic_buffer_sizes;
 
 /* Library ABI version (PIC_ABI_VERSION). */
 int pic_abi_version(void);
@@ -180,6 +189,20 @@ int pic_abi_version(void);
 pic_status pic_init(pic_ctx **ctx, const pic_grid *grid, double dx, double dt,
                     const double *wp_map, const double *gamma_map,
                     const pic_particles *particles, const pic_opts *opts);
+
+/*
+ * Device memory pic_init will need, without creating anything (no device
+ * call; callers size their own buffers for pic_opts.bufs from it, or check
+ * that a problem fits).  grid and nparticles as for pic_init; opts may be
+ * NULL and is read only for what changes the allocations: nprobe, nfreq,
+ * series_len, diag, and which entries of bufs are non-NULL (the pointers
+ * themselves are not used).  The Drude state depends on the maps: add
+ * bytes_per_metal_box_cell times the cells of the bounding box of wp > 0.
+ * pic_stats reports what a context actually allocated, for comparison.
+ * Errors: PIC_EINVAL (NULL grid or out, sizes, npml, counts out of range).
+ */
+pic_status pic_query_sizes(const pic_grid *grid, int64_t nparticles, const pic_opts *opts,
+                           pic_buffer_sizes *out);
 
 /* Advance nsteps >= 0 full time steps (H, push+deposit, Drude J + E, probes). */
 pic_status pic_step(pic_ctx *ctx, int64_t nsteps);

@@ -626,6 +626,60 @@ pic_status pic_init(pic_ctx **ctx, const pic_grid *grid, double dx, double dt, c
     return PIC_OK;
 }
 
+pic_status pic_query_sizes(const pic_grid *grid, int64_t nparticles, const pic_opts *opts,
+                           pic_buffer_sizes *out)
+{
+    if (!grid || !out) return fail(nullptr, PIC_EINVAL, "pic_query_sizes: grid and out are required");
+    const pic_grid &g = *grid;
+    const long long n[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 1) return fail(nullptr, PIC_EINVAL, "axis %d has %lld cells", d, n[d]);
+        if (g.bc[d] == PIC_BC_CPML && (g.npml < 1 || 2LL * g.npml >= n[d]))
+            return fail(nullptr, PIC_EINVAL, "npml = %d does not fit axis %d", g.npml, d);
+    }
+    const long long N = n[0] * n[1] * n[2];
+    if (N > 0x7fffffffLL) return fail(nullptr, PIC_EINVAL, "grid of %lld cells exceeds 2^31-1", N);
+    if (nparticles < 0 || nparticles > 0x7fffffffLL)
+        return fail(nullptr, PIC_EINVAL, "nparticles = %lld out of range", (long long)nparticles);
+    pic_opts o{};
+    if (opts) o = *opts;
+    if (o.nprobe < 0 || o.nfreq < 0 || o.series_len < 0)
+        return fail(nullptr, PIC_EINVAL, "nprobe, nfreq and series_len must be >= 0");
+    // what pic_init allocates, in its order (dalloc of at least one element each)
+    auto bytes = [](long long count, long long size) { return (count > 0 ? count : 1) * size; };
+    long long total = 0;
+    int given = 0;
+    for (int d = 0; d < 3; ++d)
+        given += (o.bufs && o.bufs->E[d]) + (o.bufs && o.bufs->H[0][d]) + (o.bufs && o.bufs->H[1][d]);
+    total += (9 - given) * bytes(N, 4);                       // E, H ping-pong
+    total += bytes(1, 4) + bytes(16, 8) + bytes(1, 4) + bytes(1, sizeof(pic::DevState));
+    for (int d = 0; d < 3; ++d) {                             // CPML tables and memories
+        if (g.bc[d] != PIC_BC_CPML) continue;
+        total += bytes(6 * n[d], 4) + 4 * bytes(2LL * g.npml * (N / n[d]), 4);
+    }
+    if (o.nprobe > 0) {
+        const long long nf = (long long)o.nprobe * o.nfreq;
+        total += bytes(o.nprobe, 4) + bytes(o.nfreq, 8) + 2 * bytes(nf, 8);
+        if (o.series_len > 0) total += bytes(o.series_len * o.nprobe, 4);
+    }
+    const long long np = nparticles;
+    if (np > 0) {
+        total += 2 * 6 * bytes(np, 4) + 2 * bytes(np, 4);    // particle state, ids
+        total += bytes((np + 63) / 64, 8);                    // push counters
+        total += 2 * bytes(np, 4);                            // sort keys, ranks
+        total += bytes(N + 1, 4) + bytes(6, 4);               // cell counts, box
+        total += bytes(6 * ((np + pic::PBLOCK - 1) / pic::PBLOCK), 4);
+        total += bytes(pic::scan_tmp_size(N + 1), 4);
+        total += 6 * bytes(N, 4);                             // J_b, time-centred H
+        if (o.diag) total += 2 * bytes((n[0] + 1) * (n[1] + 1) * (n[2] + 1), 8);
+    }
+    out->field_elems = N;
+    out->field_bytes = 4 * N;
+    out->device_bytes = total;
+    out->bytes_per_metal_box_cell = sizeof(float2) + 3 * sizeof(float);  // (cbt, d) + J_pol
+    return PIC_OK;
+}
+
 pic_status pic_step(pic_ctx *c, int64_t nsteps)
 {
     CHECK_CTX(c);
@@ -771,6 +825,7 @@ pic_status pic_stats(pic_ctx *c, pic_stats_out *out)
     out->steps = c->step;
     out->pushes = (int64_t)pushes;
     out->hcur = c->hcur;
+    out->device_bytes = (int64_t)c->dev_bytes;
     out->live = 0;
     for (int d = 0; d < 3; ++d) {
         out->pbox[d] = 0;

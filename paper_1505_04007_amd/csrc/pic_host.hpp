@@ -80,6 +80,7 @@ struct pic_ctx {
     bool diag = false;
     double *rho = nullptr, *rho0 = nullptr, *acc = nullptr;
     int *d_live = nullptr;
+    size_t dev_bytes = 0;  // device memory allocated through dalloc at pic_init
 
     long long step = 0;
     int tile = 0;  // field-kernel tile shape (pic_tune)
@@ -119,6 +120,7 @@ pic_status dalloc(pic_ctx *c, T **p, size_t count)
                     "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
     c->allocs.push_back(q);
+    c->dev_bytes += bytes;
     *p = (T *)q;
     return PIC_OK;
 }

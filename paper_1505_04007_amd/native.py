@@ -59,7 +59,12 @@ class PicDiag(ctypes.Structure):
 
 class PicStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("pushes", ctypes.c_int64), ("live", ctypes.c_int64),
-                ("pbox", ctypes.c_int32 * 6), ("hcur", ctypes.c_int32)]
+                ("pbox", ctypes.c_int32 * 6), ("hcur", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+class PicBufferSizes(ctypes.Structure):
+    _fields_ = [("field_elems", ctypes.c_int64), ("field_bytes", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("bytes_per_metal_box_cell", ctypes.c_int64)]
 
 
 class PicTuneOut(ctypes.Structure):
@@ -70,7 +75,7 @@ class PicTuneOut(ctypes.Structure):
 EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "pic_tune",
            "pic_read_fields", "pic_read_particles", "pic_diag", "pic_stats", "pic_timing",
            "pic_destroy", "pic_last_error", "pic_batch_create", "pic_batch_step", "pic_batch_tune",
-           "pic_batch_destroy", "pic_batch_last_error")
+           "pic_batch_destroy", "pic_batch_last_error", "pic_query_sizes")
 
 
 def _tune_dict(t):
@@ -134,6 +139,9 @@ def load():
     lib.pic_batch_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(PicTuneOut)]
     lib.pic_batch_last_error.restype = ctypes.c_char_p
     lib.pic_batch_last_error.argtypes = [vp]
+    lib.pic_query_sizes.restype = ctypes.c_int
+    lib.pic_query_sizes.argtypes = [ctypes.POINTER(PicGrid), ctypes.c_int64, ctypes.POINTER(PicOpts),
+                                    ctypes.POINTER(PicBufferSizes)]
     _LIB = lib
     return lib
 
@@ -304,7 +312,8 @@ class Simulation:
     def stats(self):
         s = PicStats()
         self._check(self._lib.pic_stats(self._h, ctypes.byref(s)))
-        return {"steps": s.steps, "pushes": s.pushes, "live": s.live, "pbox": tuple(s.pbox), "hcur": s.hcur}
+        return {"steps": s.steps, "pushes": s.pushes, "live": s.live, "pbox": tuple(s.pbox), "hcur": s.hcur,
+                "device_bytes": s.device_bytes}
 
     def device_E(self):
         """E (V/m) as a torch tensor (3, nz, ny, nx) on the GPU, the library's own
@@ -367,6 +376,39 @@ def spp_power(make_sim, omega0, nsteps, ckpt_every=0):
             return g * gw, g * gg
 
     return SppPower.apply
+
+
+def query_sizes(nx, ny, nz, bc=(BC_PEC,) * 3, npml=0, pml=(3.0, 1.0, 1.0, 0.0), nparticles=0,
+                nprobe=0, nfreq=0, series_len=0, diag=False, device_fields=False):
+    """pic_query_sizes: device memory pic_init needs (a dict of pic_buffer_sizes).
+
+    device_fields=True counts E and H as caller memory (as Simulation(...,
+    device_fields=True) provides them); only whether those entries are set
+    matters to the query, so placeholders stand in for the pointers."""
+    lib = load()
+    g = PicGrid(nx, ny, nz, (ctypes.c_int32 * 3)(*[int(b) for b in bc]), int(npml), *pml)
+    o = PicOpts()
+    o.nprobe, o.nfreq, o.series_len, o.diag = int(nprobe), int(nfreq), int(series_len), int(bool(diag))
+    if device_fields:
+        bufs = PicDeviceBuffers()
+        for d in range(3):
+            bufs.E[d] = 4 * (3 * d + 1)
+            for p in range(2):
+                bufs.H[p][d] = 4 * (3 * d + 2 + p)
+        o.bufs = ctypes.pointer(bufs)
+    out = PicBufferSizes()
+    st = lib.pic_query_sizes(ctypes.byref(g), int(nparticles), ctypes.byref(o), ctypes.byref(out))
+    if st != PIC_OK:
+        raise PicError(st, lib.pic_last_error(None).decode())
+    return {"field_elems": out.field_elems, "field_bytes": out.field_bytes, "device_bytes": out.device_bytes,
+            "bytes_per_metal_box_cell": out.bytes_per_metal_box_cell}
+
+
+def workload_sizes(w, with_bunch=True, **kw):
+    """query_sizes for a pic_inputs.Workload, with what from_workload passes."""
+    return query_sizes(w.nx, w.ny, w.nz, bc=w.bc, npml=w.npml, pml=w.pml,
+                       nparticles=w.bunch.n if (with_bunch and w.bunch is not None) else 0,
+                       nprobe=len(w.probes), nfreq=len(w.omega), **kw)
 
 
 def from_workload(w, with_bunch=True, **kw):

@@ -44,17 +44,55 @@ def test_library_exports_only_the_declared_c_entry_points():
     assert c_names == set(_declared())
 
 
+STRUCTS = {"pic_grid": "PicGrid", "pic_particles": "PicParticles", "pic_device_buffers": "PicDeviceBuffers",
+           "pic_opts": "PicOpts", "pic_diag_out": "PicDiag", "pic_stats_out": "PicStats",
+           "pic_buffer_sizes": "PicBufferSizes", "pic_tune_out": "PicTuneOut"}
+
+
+def _header_fields(src, name):
+    """Member names of `typedef struct {...} name;` in declaration order."""
+    end = src.index("} %s;" % name)
+    body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"): end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = re.sub(r"\[[^\]]*\]", "", decl).strip()
+        if not decl:
+            continue
+        parts = decl.split(",")
+        names.append(re.findall(r"\w+", parts[0])[-1])
+        names += [re.findall(r"\w+", q)[-1] for q in parts[1:]]
+    return names
+
+
 def test_binding_structs_and_buffers_match_the_header():
-    """The ctypes mirrors of pic_opts and of pic_timing's output arrays have the
-    header's field count and length (a short buffer is overrun by the library)."""
+    """Every ctypes mirror has the header struct's members in order and its
+    size as the C compiler lays it out, and pic_timing's output arrays have the
+    header's length (a short buffer is overrun by the library)."""
+    import shutil
+    import subprocess
+    import tempfile
     src = open(os.path.join(ROOT, "include", "pic.h")).read()
     n_fam = int(re.search(r"ms_total\[(\d+)\], launches\[(\d+)\]", src).group(1))
     assert n_fam == len(native.KERNEL_FAMILIES)
-    end = src.index("} pic_opts;")
-    body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"): end]
-    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    fields = re.findall(r"(\w+)(?:\[\d+\])?\s*;", body)
-    assert fields == [f[0] for f in native.PicOpts._fields_]
+    for cname, pyname in STRUCTS.items():
+        py = getattr(native, pyname)
+        assert _header_fields(src, cname) == [f[0] for f in py._fields_], cname
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    with tempfile.TemporaryDirectory() as d:
+        prog = os.path.join(d, "sizes.c")
+        with open(prog, "w") as f:
+            f.write('#include <stdio.h>\n#include "pic.h"\nint main(void) {\n')
+            for cname in STRUCTS:
+                f.write('    printf("%%s %%zu\\n", "%s", sizeof(%s));\n' % (cname, cname))
+            f.write("    return 0;\n}\n")
+        exe = os.path.join(d, "sizes")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), prog, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    for line in out.splitlines():
+        cname, size = line.split()
+        assert ctypes.sizeof(getattr(native, STRUCTS[cname])) == int(size), cname
 
 
 def _init(**over):
@@ -143,3 +181,28 @@ def test_product_binding_has_no_cpu_fallback():
     """The binding only marshals arguments into libpic.so: it never imports the oracle."""
     src = open(os.path.join(ROOT, "paper_1505_04007_amd", "native.py")).read()
     assert "oracle" not in src.replace("Importing it fails loudly", "")
+
+
+def test_query_sizes_without_a_device():
+    """pic_query_sizes answers on the host: per-array sizes, caller-held E and H
+    removed from the total, particles adding at least their own state, and
+    the same argument checks as pic_init."""
+    q = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
+                           nparticles=0, nprobe=3, nfreq=16)
+    N = 40 * 24 * 30
+    assert q["field_elems"] == N and q["field_bytes"] == 4 * N
+    assert q["bytes_per_metal_box_cell"] == 20
+    assert q["device_bytes"] >= 9 * 4 * N
+    own = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
+                             nparticles=0, nprobe=3, nfreq=16, device_fields=True)
+    assert q["device_bytes"] - own["device_bytes"] == 9 * 4 * N
+    withp = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
+                               nparticles=1000, nprobe=3, nfreq=16)
+    assert withp["device_bytes"] - q["device_bytes"] >= 1000 * 2 * 7 * 4 + 6 * 4 * N
+    for kw, frag in ((dict(nx=2048, ny=1024, nz=1024), "2^31-1"),
+                     (dict(bc=(native.BC_CPML,) * 3, npml=20), "npml"),
+                     (dict(nparticles=-1), "nparticles")):
+        args = dict(nx=40, ny=24, nz=30)
+        args.update(kw)
+        with pytest.raises(native.PicError, match=re.escape(frag)):
+            native.query_sizes(args.pop("nx"), args.pop("ny"), args.pop("nz"), **args)

@@ -133,7 +133,12 @@ typedef struct {
                                  normal entries on PEC/CPML walls are taken as 0 */
     int32_t diag;             /* 1: keep the FP64 charge grid needed by the Gauss check */
     int32_t timing;           /* 1: time every kernel launch with HIP events */
-    int32_t deposit_mode;     /* 0: wavefront-reduced deposit (default), 1: per-lane atomics */
+    int32_t deposit_mode;     /* 0: wavefront-reduced deposit (default), 1: per-lane atomics,
+                                 2: wavefront-reduced into a 64-bit fixed-point current
+                                 (each particle's edge currents rounded to 2^-24 of the
+                                 largest one particle can deposit, then summed exactly, so
+                                 runs are bitwise reproducible; not in batches, nor in
+                                 pic_grad with checkpoints) */
     const pic_device_buffers *bufs;  /* optional caller device memory for E and H; NULL = none */
 } pic_opts;
 
@@ -246,7 +251,8 @@ pic_status pic_probe(pic_ctx *ctx, double *re, double *im, double *series);
  *   dL_dgamma  : out [nx*ny*nz], per 1/s; may be NULL
  * Both maps are 0 outside cells with wp > 0.  Synchronises the stream.
  * Errors: PIC_EINVAL (nsteps < 1, ckpt_every < 0, no probes, L NULL,
- * omega0 not finite), PIC_ENOMEM, PIC_EDEVICE, PIC_EUNSTABLE.  After an
+ * omega0 not finite), PIC_ENOTSUP (checkpoints with deposit_mode 2: the
+ * recorded current is FP32), PIC_ENOMEM, PIC_EDEVICE, PIC_EUNSTABLE.  After an
  * error other than PIC_EINVAL the simulation may stand at any step of the
  * call's forward run.
  */
@@ -308,12 +314,13 @@ void pic_destroy(pic_ctx *ctx);
  *
  * pic_batch_create: ctxs[0..n) are existing contexts (1 <= n <= 64) created
  *   on one stream; those with particles must share sort_every and
- *   deposit_mode.  The batch borrows them: they must outlive it and stay
- *   valid; reading them (pic_probe, pic_read_*, pic_diag, ...) between batch
- *   steps is allowed.  use_graph = 1 captures one sort period (sort_every
- *   steps and the sorts that follow, or 10 steps without particles) as a HIP
- *   graph at creation and replays it whenever all members are at the start
- *   of a sort period; other steps are issued directly.
+ *   deposit_mode (0 or 1; deposit_mode 2 gives PIC_ENOTSUP).  The batch
+ *   borrows them: they must outlive it and stay valid; reading them
+ *   (pic_probe, pic_read_*, pic_diag, ...) between batch steps is allowed.
+ *   use_graph = 1 captures one sort period (sort_every steps and the sorts
+ *   that follow, or 10 steps without particles) as a HIP graph at creation
+ *   and replays it whenever all members are at the start of a sort period;
+ *   other steps are issued directly.
  * pic_batch_step: advance every member by nsteps steps.  Each member's
  *   results equal those of pic_step on that member alone (same kernels, same
  *   per-cell arithmetic).  No non-finite poll is made; use pic_diag.

@@ -221,12 +221,22 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
         nez -= jz;
     }
     if (a.pbox && in_particle_box(a, margin, i, j, k)) {
-        nex -= a.Jb[0][id];
-        ney -= a.Jb[1][id];
-        nez -= a.Jb[2][id];
-        a.Jb[0][id] = 0.f;
-        a.Jb[1][id] = 0.f;
-        a.Jb[2][id] = 0.f;
+        if (a.Jq[0]) {
+            // fixed-point bunch current (deterministic deposit), FP64 to V/m
+            nex -= (float)((double)(long long)a.Jq[0][id] * a.qinv);
+            ney -= (float)((double)(long long)a.Jq[1][id] * a.qinv);
+            nez -= (float)((double)(long long)a.Jq[2][id] * a.qinv);
+            a.Jq[0][id] = 0ull;
+            a.Jq[1][id] = 0ull;
+            a.Jq[2][id] = 0ull;
+        } else {
+            nex -= a.Jb[0][id];
+            ney -= a.Jb[1][id];
+            nez -= a.Jb[2][id];
+            a.Jb[0][id] = 0.f;
+            a.Jb[1][id] = 0.f;
+            a.Jb[2][id] = 0.f;
+        }
     }
     const bool wx = !a.per[0] && i == 0, wy = !a.per[1] && j == 0, wz = !a.per[2] && k == 0;
     if (!(wy || wz)) st_once(a.E[0] + id, nex);

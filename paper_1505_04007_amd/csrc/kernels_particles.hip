@@ -228,20 +228,48 @@ __device__ __forceinline__ float slot_value(const Dep &d, int s, float f)
     return f * d.pre[2][ok] * d.Txy[oi][oj];
 }
 
-__device__ __forceinline__ float *slot_addr(const PartArgs &a, int s, int bx, int by, int bz)
+// Cell index of slot s of the window at (bx, by, bz) after wrapping, or -1
+// when it falls outside the grid on a non-periodic axis.
+__device__ __forceinline__ int slot_index(const PartArgs &a, int s, int bx, int by, int bz, int &comp)
 {
-    int comp, oi, oj, ok;
+    int oi, oj, ok;
     slot_geom(s, comp, oi, oj, ok);
     int i = bx + oi, j = by + oj, k = bz + ok;
     if (a.per[0]) i = wrapn(i, a.nx);
-    else if (i < 0 || i >= a.nx) return nullptr;
+    else if (i < 0 || i >= a.nx) return -1;
     if (a.per[1]) j = wrapn(j, a.ny);
-    else if (j < 0 || j >= a.ny) return nullptr;
+    else if (j < 0 || j >= a.ny) return -1;
     if (a.per[2]) k = wrapn(k, a.nz);
-    else if (k < 0 || k >= a.nz) return nullptr;
+    else if (k < 0 || k >= a.nz) return -1;
+    return i + a.nx * (j + a.ny * k);
+}
+
+__device__ __forceinline__ float *slot_addr(const PartArgs &a, int s, int bx, int by, int bz)
+{
+    int comp;
+    const int q = slot_index(a, s, bx, by, bz, comp);
+    if (q < 0) return nullptr;
     // select, not a[comp]: a runtime index into the argument block would put it in scratch
     float *J = comp == 0 ? a.Jb[0] : (comp == 1 ? a.Jb[1] : a.Jb[2]);
-    return J + (i + a.nx * (j + a.ny * k));
+    return J + q;
+}
+
+// Fixed-point deposit: each particle's slot currents are rounded to integer
+// units (qscale per V/m, at most 2^24 per slot) before anything is summed, so
+// the wavefront sums (at most 2^30) and the 64-bit atomics are exact and the
+// result does not depend on which lanes share a round or on atomic order.
+__device__ __forceinline__ void add_fixed(const PartArgs &a, int comp, int q, int units)
+{
+    unsigned long long *J = comp == 0 ? a.Jq[0] : (comp == 1 ? a.Jq[1] : a.Jq[2]);
+    atomicAdd(J + q, (unsigned long long)(long long)units);
+}
+
+// Sum of two slot values: FP32, or the int32 fixed-point units held in the
+// same registers.
+template <int INT>
+__device__ __forceinline__ float add2(float x, float y)
+{
+    return INT ? __int_as_float(__float_as_int(x) + __float_as_int(y)) : x + y;
 }
 
 // Lane l receives x from lane l ^ OFF (OFF = 8, 4, 2, 1), by DPP row moves.
@@ -264,7 +292,7 @@ __device__ __forceinline__ float xor_lane(float x)
     return __int_as_float(r);
 }
 
-template <int OFF>
+template <int OFF, int INT>
 __device__ __forceinline__ void halve_dpp(float *v, int lane)
 {
     const bool up = (lane & OFF) != 0;
@@ -272,7 +300,7 @@ __device__ __forceinline__ void halve_dpp(float *v, int lane)
     for (int e = 0; e < OFF; ++e) {
         const float send = up ? v[e] : v[e + OFF];
         const float keep = up ? v[e + OFF] : v[e];
-        v[e] = keep + xor_lane<OFF>(send);
+        v[e] = add2<INT>(keep, xor_lane<OFF>(send));
     }
 }
 
@@ -281,6 +309,7 @@ __device__ __forceinline__ void halve_dpp(float *v, int lane)
 // partner values next to its own, and the sum finishes the round.  The first
 // round reads the 54 slot currents of a lane, or zeros for a lane outside
 // the round's window.
+template <int INT>
 __device__ __forceinline__ void halve32(const float *val, bool mine, float *v)
 {
 #pragma unroll
@@ -288,31 +317,33 @@ __device__ __forceinline__ void halve32(const float *val, bool mine, float *v)
         const float lo = mine ? val[e] : 0.f;
         const float hi = (e + 32 < 54 && mine) ? val[e + 32 < 54 ? e + 32 : 0] : 0.f;
         const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
-        v[e] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        v[e] = add2<INT>(__uint_as_float(r[0]), __uint_as_float(r[1]));
     }
 }
 
+template <int INT>
 __device__ __forceinline__ void halve16(float *v)
 {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[e]), __float_as_uint(v[e + 16]),
                                                         false, false);
-        v[e] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        v[e] = add2<INT>(__uint_as_float(r[0]), __uint_as_float(r[1]));
     }
 }
 
 // After the six rounds lane l holds the sum of slot l over the lanes with
 // `mine` set.
+template <int INT>
 __device__ __forceinline__ float wave_reduce64(const float *val, bool mine, int lane)
 {
     float v[32];
-    halve32(val, mine, v);
-    halve16(v);
-    halve_dpp<8>(v, lane);
-    halve_dpp<4>(v, lane);
-    halve_dpp<2>(v, lane);
-    halve_dpp<1>(v, lane);
+    halve32<INT>(val, mine, v);
+    halve16<INT>(v);
+    halve_dpp<8, INT>(v, lane);
+    halve_dpp<4, INT>(v, lane);
+    halve_dpp<2, INT>(v, lane);
+    halve_dpp<1, INT>(v, lane);
     return v[0];
 }
 
@@ -322,7 +353,7 @@ __device__ __forceinline__ float wave_reduce64(const float *val, bool mine, int 
 // wavefront together (54 atomic instructions however many lanes).
 constexpr int ROUND_LANES = 3;
 
-template <int MODE, int PX>
+template <int MODE, int PX, int FIX>
 __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
 {
     const int p = blk * PUSH_BLOCK + threadIdx.x;
@@ -417,6 +448,12 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
     float val[54];
 #pragma unroll
     for (int s = 0; s < 54; ++s) val[s] = slot_value(d, s, qd);
+    if (FIX) {
+        // integer units per slot, kept in the same registers
+        const float qs = a.qscale;
+#pragma unroll
+        for (int s = 0; s < 54; ++s) val[s] = __int_as_float(__float2int_rn(val[s] * qs));
+    }
     const unsigned long long live = __ballot(dep);
     // per-wavefront push counter (one slot per wavefront of the launch)
     if (lane == 0 && live) a.pushes[p >> 6] += (unsigned long long)__popcll(live);
@@ -440,15 +477,22 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                 small |= m;
                 continue;
             }
-            const float tot = wave_reduce64(val, mine, lane);
+            const float tot = wave_reduce64<FIX>(val, mine, lane);
             const int bx = __builtin_amdgcn_readlane(base[0], leader);
             const int by = __builtin_amdgcn_readlane(base[1], leader);
             const int bz = __builtin_amdgcn_readlane(base[2], leader);
-            if (lane < 54 && tot != 0.f) {
+            if (lane < 54 && (FIX ? __float_as_int(tot) != 0 : tot != 0.f)) {
                 const bool inside = bx >= 0 && bx + 2 < a.nx && by >= 0 && by + 2 < a.ny && bz >= 0 &&
                                     bz + 2 < a.nz;
-                float *ad = inside ? Jl + (bx + a.nx * (by + a.ny * bz)) + lrel : slot_addr(a, lane, bx, by, bz);
-                if (ad) atomicAdd(ad, tot);
+                if (FIX) {
+                    int comp = lc;
+                    const int q = inside ? (bx + a.nx * (by + a.ny * bz)) + lrel
+                                         : slot_index(a, lane, bx, by, bz, comp);
+                    if (q >= 0) add_fixed(a, comp, q, __float_as_int(tot));
+                } else {
+                    float *ad = inside ? Jl + (bx + a.nx * (by + a.ny * bz)) + lrel : slot_addr(a, lane, bx, by, bz);
+                    if (ad) atomicAdd(ad, tot);
+                }
             }
         }
         rem = small;
@@ -464,15 +508,25 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
             for (int s = 0; s < 54; ++s) {
                 int comp, oi, oj, ok;
                 slot_geom(s, comp, oi, oj, ok);
-                float *J = comp == 0 ? a.Jb[0] : (comp == 1 ? a.Jb[1] : a.Jb[2]);
                 const float v = val[s];
-                if (v != 0.f) atomicAdd(J + lin + (oi + sy * oj + sz * ok), v);
+                if (FIX) {
+                    const int u = __float_as_int(v);
+                    if (u != 0) add_fixed(a, comp, lin + (oi + sy * oj + sz * ok), u);
+                } else {
+                    float *J = comp == 0 ? a.Jb[0] : (comp == 1 ? a.Jb[1] : a.Jb[2]);
+                    if (v != 0.f) atomicAdd(J + lin + (oi + sy * oj + sz * ok), v);
+                }
             }
         } else {
 #pragma unroll
             for (int s = 0; s < 54; ++s) {
                 const float v = val[s];
-                if (v != 0.f) {
+                if (FIX) {
+                    const int u = __float_as_int(v);
+                    int comp;
+                    const int q = u != 0 ? slot_index(a, s, base[0], base[1], base[2], comp) : -1;
+                    if (q >= 0) add_fixed(a, comp, q, u);
+                } else if (v != 0.f) {
                     float *ad = slot_addr(a, s, base[0], base[1], base[2]);
                     if (ad) atomicAdd(ad, v);
                 }
@@ -481,10 +535,10 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
     }
 }
 
-template <int MODE, int PX>
+template <int MODE, int PX, int FIX>
 __global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit(PartArgs a)
 {
-    push_body<MODE, PX>(a, blockIdx.x);
+    push_body<MODE, PX, FIX>(a, blockIdx.x);
 }
 
 // Many simulations in one launch: workgroup b belongs to the simulation q
@@ -496,19 +550,23 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit_batch(const PartArg
     const int b = blockIdx.x;
     int q = 0;
     while (q + 1 < n && start[q + 1] <= b) ++q;
-    push_body<MODE, PX>(args[q], b - start[q]);
+    push_body<MODE, PX, 0>(args[q], b - start[q]);
 }
 
 void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s)
 {
     if (a.n <= 0) return;
     const int nb = (int)(((long long)a.n + PUSH_BLOCK - 1) / PUSH_BLOCK);
+    // mode 2: wavefront-reduced deposit into the fixed-point current
+    const bool fix = mode == 2 && a.Jq[0];
     if (a.per[0]) {
-        if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 1>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
-        else hipLaunchKernelGGL((k_push_deposit<0, 1>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
+        if (fix) hipLaunchKernelGGL((k_push_deposit<0, 1, 1>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
+        else if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 1, 0>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_push_deposit<0, 1, 0>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
     } else {
-        if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 0>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
-        else hipLaunchKernelGGL((k_push_deposit<0, 0>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
+        if (fix) hipLaunchKernelGGL((k_push_deposit<0, 0, 1>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
+        else if (mode == 1) hipLaunchKernelGGL((k_push_deposit<1, 0, 0>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_push_deposit<0, 0, 0>), dim3(nb), dim3(PUSH_BLOCK), 0, s, a);
     }
 }
 

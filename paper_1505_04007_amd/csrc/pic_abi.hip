@@ -104,7 +104,9 @@ void build_args(pic_ctx *c)
         a.Havg[d] = c->Havg[d];
         a.Jp[d] = c->Jp[d];
         a.Jb[d] = c->Jb[d];
+        a.Jq[d] = c->Jq[d];
     }
+    a.qinv = c->qinv;
     a.coef = c->coef;
     a.pbox = c->np > 0 ? c->box : nullptr;
     a.nan_flag = c->d_nan;
@@ -123,7 +125,9 @@ void build_args(pic_ctx *c)
         pa.E[d] = c->E[d];
         pa.B[d] = c->Havg[d];
         pa.Jb[d] = c->Jb[d];
+        pa.Jq[d] = c->Jq[d];
     }
+    pa.qscale = (float)c->qscale;
     pa.S = (float)c->S;
     pa.ah = c->ah;
     pa.qd = c->qd;
@@ -336,7 +340,9 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
     c->check_every = o.check_every > 0 ? o.check_every : 0;
     c->timing = o.timing != 0;
     c->diag = o.diag != 0;
-    c->deposit_mode = o.deposit_mode == 1 ? 1 : 0;
+    if (o.deposit_mode < 0 || o.deposit_mode > 2)
+        return fail(c, PIC_EINVAL, "deposit_mode = %d is not 0, 1 or 2", o.deposit_mode);
+    c->deposit_mode = o.deposit_mode;
     if (o.nprobe < 0 || o.nfreq < 0 || o.series_len < 0)
         return fail(c, PIC_EINVAL, "nprobe, nfreq and series_len must be >= 0");
     if (o.nprobe > 256) return fail(c, PIC_EINVAL, "at most 256 probes");
@@ -581,9 +587,22 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         TRY(dalloc(c, &c->boxpart, 6 * (((size_t)c->np + pic::PBLOCK - 1) / pic::PBLOCK)));
         c->scan_len = pic::scan_tmp_size(ncell + 1);
         TRY(dalloc(c, &c->scan_tmp, (size_t)c->scan_len));
+        if (c->deposit_mode == 2) {
+            // fixed point: 2^24 units per the largest current one particle can
+            // put on an edge (|qd|), so a wavefront's sum fits in 31 bits and
+            // 2^39 such contributions in an edge's 64-bit total
+            const double unit = std::fabs((double)c->qd);
+            c->qscale = (double)(float)(unit > 0.0 ? 16777216.0 / unit : 1.0);
+            c->qinv = 1.0 / c->qscale;
+        }
         for (int d = 0; d < 3; ++d) {
-            TRY(dalloc(c, &c->Jb[d], N));
-            HIP_TRY(c, hipMemsetAsync(c->Jb[d], 0, N * 4, c->stream));
+            if (c->deposit_mode == 2) {
+                TRY(dalloc(c, &c->Jq[d], N));
+                HIP_TRY(c, hipMemsetAsync(c->Jq[d], 0, N * 8, c->stream));
+            } else {
+                TRY(dalloc(c, &c->Jb[d], N));
+                HIP_TRY(c, hipMemsetAsync(c->Jb[d], 0, N * 4, c->stream));
+            }
             TRY(dalloc(c, &c->Havg[d], N));
             HIP_TRY(c, hipMemsetAsync(c->Havg[d], 0, N * 4, c->stream));
         }
@@ -670,7 +689,8 @@ pic_status pic_query_sizes(const pic_grid *grid, int64_t nparticles, const pic_o
         total += bytes(N + 1, 4) + bytes(6, 4);               // cell counts, box
         total += bytes(6 * ((np + pic::PBLOCK - 1) / pic::PBLOCK), 4);
         total += bytes(pic::scan_tmp_size(N + 1), 4);
-        total += 6 * bytes(N, 4);                             // J_b, time-centred H
+        total += 3 * bytes(N, o.deposit_mode == 2 ? 8 : 4);   // J_b (fixed point: 64-bit)
+        total += 3 * bytes(N, 4);                             // time-centred H
         if (o.diag) total += 2 * bytes((n[0] + 1) * (n[1] + 1) * (n[2] + 1), 8);
     }
     out->field_elems = N;
@@ -725,6 +745,12 @@ pic_status pic_read_fields(pic_ctx *c, int which, double *out)
         if (which == PIC_FIELD_E || which == PIC_FIELD_H || which == PIC_FIELD_JB) {
             const float *src = which == PIC_FIELD_E ? c->E[d] : which == PIC_FIELD_H ? c->H[c->hcur][d] : c->Jb[d];
             const double sc = which == PIC_FIELD_H ? 1.0 / kEta0 : which == PIC_FIELD_JB ? kEps0 / c->dt : 1.0;
+            if (which == PIC_FIELD_JB && c->Jq[d]) {
+                std::vector<long long> q(N);
+                HIP_TRY(c, hipMemcpy(q.data(), c->Jq[d], N * 8, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < N; ++i) dst[i] = (double)q[i] * c->qinv * sc;
+                continue;
+            }
             if (!src) {
                 for (size_t q = 0; q < N; ++q) dst[q] = 0.0;
                 continue;

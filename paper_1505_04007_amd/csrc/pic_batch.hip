@@ -155,6 +155,8 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
         if (q > 0 && c->stream != ctxs[0]->stream)
             return bfail(b, PIC_EINVAL, "all contexts must share one stream");
         if (c->np > 0) {
+            if (c->deposit_mode == 2)
+                return bfail(b, PIC_ENOTSUP, "context %d uses the fixed-point deposit, which batches do not run", q);
             if (b->particles && (c->sort_every != b->sort_every || (b->push_mode & 1) != c->deposit_mode))
                 return bfail(b, PIC_EINVAL, "contexts with particles must share sort_every and deposit_mode");
             b->particles = true;

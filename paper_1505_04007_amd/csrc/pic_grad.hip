@@ -450,6 +450,10 @@ pic_status pic_grad(pic_ctx *c, double omega0, int64_t nsteps, int64_t ckpt_ever
         const double need = (double)nsteps * 6.0 * (double)c->nbox * 4.0;
         store_all = need <= 0.5 * (double)freeb;
     }
+    if (!store_all && c->np > 0 && c->deposit_mode == 2)
+        return fail(c, PIC_ENOTSUP,
+                    "pic_grad with checkpoints records the FP32 bunch current: not available with the "
+                    "fixed-point deposit (deposit_mode 2); use ckpt_every = 0 with enough device memory");
     return grad_impl(c, omega0, (long long)nsteps, K, store_all, L, dL_dwp, dL_dgamma);
 }
 

@@ -80,6 +80,9 @@ struct pic_ctx {
     bool diag = false;
     double *rho = nullptr, *rho0 = nullptr, *acc = nullptr;
     int *d_live = nullptr;
+    // deposit_mode 2: the bunch current in fixed point (units per V/m and back)
+    unsigned long long *Jq[3] = {nullptr, nullptr, nullptr};
+    double qscale = 0.0, qinv = 0.0;
     size_t dev_bytes = 0;  // device memory allocated through dalloc at pic_init
 
     long long step = 0;

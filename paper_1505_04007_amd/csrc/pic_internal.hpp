@@ -86,6 +86,8 @@ struct FieldArgs {
     float *snap;
     // bunch current: read and cleared inside the particle box (+ margin)
     float *Jb[3];
+    unsigned long long *Jq[3];  // the fixed-point form instead of Jb, or null
+    double qinv;                // V/m per fixed-point unit
     const int *pbox;  // device [6]: lo x,y,z, hi x,y,z (cells, inclusive), or null
     int *nan_flag;
     DevState *st;
@@ -99,6 +101,11 @@ struct PartArgs {
     const float *E[3];
     const float *B[3];  // (Ht^{n-1/2} + Ht^{n+1/2}) / 2, valid inside the particle box
     float *Jb[3];
+    // fixed-point bunch current (deterministic deposit): integer atomics of
+    // round(current * qscale) per particle and slot, or null for the FP32
+    // atomics into Jb
+    unsigned long long *Jq[3];
+    float qscale;
     float S;   // c dt / dx
     float ah;  // q dt / (2 m c), per V/m
     float qd;  // -q w / (eps0 dx^2), V/m

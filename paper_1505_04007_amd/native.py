@@ -379,7 +379,7 @@ def spp_power(make_sim, omega0, nsteps, ckpt_every=0):
 
 
 def query_sizes(nx, ny, nz, bc=(BC_PEC,) * 3, npml=0, pml=(3.0, 1.0, 1.0, 0.0), nparticles=0,
-                nprobe=0, nfreq=0, series_len=0, diag=False, device_fields=False):
+                nprobe=0, nfreq=0, series_len=0, diag=False, device_fields=False, deposit_mode=0):
     """pic_query_sizes: device memory pic_init needs (a dict of pic_buffer_sizes).
 
     device_fields=True counts E and H as caller memory (as Simulation(...,
@@ -389,6 +389,7 @@ def query_sizes(nx, ny, nz, bc=(BC_PEC,) * 3, npml=0, pml=(3.0, 1.0, 1.0, 0.0), 
     g = PicGrid(nx, ny, nz, (ctypes.c_int32 * 3)(*[int(b) for b in bc]), int(npml), *pml)
     o = PicOpts()
     o.nprobe, o.nfreq, o.series_len, o.diag = int(nprobe), int(nfreq), int(series_len), int(bool(diag))
+    o.deposit_mode = int(deposit_mode)
     if device_fields:
         bufs = PicDeviceBuffers()
         for d in range(3):

@@ -199,6 +199,9 @@ def test_query_sizes_without_a_device():
     withp = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
                                nparticles=1000, nprobe=3, nfreq=16)
     assert withp["device_bytes"] - q["device_bytes"] >= 1000 * 2 * 7 * 4 + 6 * 4 * N
+    fixed = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
+                               nparticles=1000, nprobe=3, nfreq=16, deposit_mode=2)
+    assert fixed["device_bytes"] - withp["device_bytes"] == 3 * 4 * N  # 64-bit bunch current
     for kw, frag in ((dict(nx=2048, ny=1024, nz=1024), "2^31-1"),
                      (dict(bc=(native.BC_CPML,) * 3, npml=20), "npml"),
                      (dict(nparticles=-1), "nparticles")):

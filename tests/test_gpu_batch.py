@@ -109,3 +109,11 @@ def test_batch_rejects_mismatched_members():
     assert ei.value.status == native.PIC_EINVAL
     with pytest.raises(native.PicError):
         native.Batch([sims[0], sims[0]])
+
+
+def test_batch_rejects_the_fixed_point_deposit():
+    w, E = _members(True, sort_every=10)[0]
+    sim = native.from_workload(w, init_E=E, deposit_mode=2)
+    with pytest.raises(native.PicError) as ei:
+        native.Batch([sim])
+    assert ei.value.status == native.PIC_ENOTSUP

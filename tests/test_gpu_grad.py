@@ -245,3 +245,20 @@ def test_spp_power_autograd_function():
     assert float(L.detach()) == L2
     assert np.array_equal(wp.grad.numpy(), 3.0 * gw)
     assert np.array_equal(g.grad.numpy(), 3.0 * gg)
+
+
+def test_fixed_point_deposit_gradient():
+    """With the fixed-point deposit the store-all reverse pass gives the FP32
+    deposit's gradient to rounding; the checkpointed one is refused."""
+    w = pi.film_adjoint(nparticles=2000)
+    w0 = w.meta["omega0"]
+    a = native.from_workload(w)
+    b = native.from_workload(w, deposit_mode=2)
+    La, ga, _ = a.grad(w0, 60)
+    Lb, gb, _ = b.grad(w0, 60)
+    assert abs(Lb - La) <= 1e-4 * abs(La)
+    assert np.linalg.norm(gb - ga) <= 1e-3 * np.linalg.norm(ga)
+    c = native.from_workload(w, deposit_mode=2)
+    with pytest.raises(native.PicError) as e:
+        c.grad(w0, 60, ckpt_every=7)
+    assert e.value.status == native.PIC_ENOTSUP

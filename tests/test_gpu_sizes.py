@@ -39,6 +39,7 @@ CASES = {
     "fields_only": (lambda: _ragged(False), {}),
     "bunch_series_diag": (lambda: _ragged(True), dict(series_len=40, diag=True)),
     "bunch_device_fields": (lambda: _ragged(True), dict(device_fields=True)),
+    "bunch_fixed_point": (lambda: _ragged(True), dict(deposit_mode=2)),
     "pec_slab_tiny": (pi.slab_tiny, {}),
 }
 

@@ -301,6 +301,8 @@ pic_status pic_stats(pic_ctx *ctx, pic_stats_out *out);
  *   0 h_update, 1 push_deposit, 2 e_update, 3 probe, 4 sort.
  * ms_total[5], launches[5] receive the accumulated milliseconds and launch
  * counts since init or the last reset; reset = 1 clears them afterwards.
+ * The context holds two HIP events per timed launch until a reset: in a
+ * long timed run, call with reset = 1 from time to time.
  */
 pic_status pic_timing(pic_ctx *ctx, double *ms_total, int64_t *launches, int reset);
 

@@ -167,20 +167,33 @@ void build_args(pic_ctx *c)
     pr.st = c->dstate;
 }
 
+// Launch timing (opts.timing): a pair of events around each launch.  A pair
+// that cannot be created is skipped (that launch goes untimed) rather than
+// recorded with invalid handles.
 void tstart(pic_ctx *c, int fam)
 {
+    c->timed_now = false;
     if (!c->timing) return;
-    hipEvent_t a, b;
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(a);
+        return;
+    }
     (void)hipEventRecord(a, c->stream);
     c->ev[fam].push_back({a, b});
+    c->timed_now = true;
 }
 
 void tstop(pic_ctx *c, int fam)
 {
-    if (!c->timing) return;
+    if (!c->timing || !c->timed_now) return;
     (void)hipEventRecord(c->ev[fam].back().second, c->stream);
+    c->timed_now = false;
 }
 
 pic_status do_sort(pic_ctx *c)

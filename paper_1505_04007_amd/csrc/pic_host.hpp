@@ -84,6 +84,7 @@ struct pic_ctx {
     unsigned long long *Jq[3] = {nullptr, nullptr, nullptr};
     double qscale = 0.0, qinv = 0.0;
     size_t dev_bytes = 0;  // device memory allocated through dalloc at pic_init
+    bool timed_now = false;  // the launch being issued has a start event
 
     long long step = 0;
     int tile = 0;  // field-kernel tile shape (pic_tune)

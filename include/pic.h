@@ -209,7 +209,16 @@ pic_status pic_init(pic_ctx **ctx, const pic_grid *grid, double dx, double dt,
 pic_status pic_query_sizes(const pic_grid *grid, int64_t nparticles, const pic_opts *opts,
                            pic_buffer_sizes *out);
 
-/* Advance nsteps >= 0 full time steps (H, push+deposit, Drude J + E, probes). */
+/*
+ * Advance nsteps >= 0 full time steps, each in the order of Sec. II (the
+ * text after Eq. 8): the H update in its vacuum form, the bunch push and
+ * current deposit (gather, Boris, move, Esirkepov), the Drude current of
+ * Eq. 6 from E^n, the E update of Eq. 8 less both currents, then the probe
+ * DFT.  The particles are re-sorted by cell every sort_every steps.
+ * Asynchronous on the context's stream, except for the non-finite poll every
+ * check_every steps (PIC_EUNSTABLE, context poisoned, when it finds one).
+ * Errors: PIC_EINVAL (nsteps < 0), PIC_ESTATE, PIC_EDEVICE, PIC_EUNSTABLE.
+ */
 pic_status pic_step(pic_ctx *ctx, int64_t nsteps);
 
 /*
@@ -282,7 +291,13 @@ typedef struct {
  */
 pic_status pic_tune(pic_ctx *ctx, int32_t reps, int32_t force, pic_tune_out *out);
 
-/* Copy one field (3 components, compact Yee layout, SI units) to host. */
+/*
+ * Copy one field to host: host_out[3*nx*ny*nz], the three components one after
+ * another in the compact Yee layout, SI units (E V/m, H A/m, J_pol and J_b
+ * A/m^2; J_pol is the current of Eq. 6, zero outside the metal box).
+ * Synchronises the stream.  Errors: PIC_EINVAL (unknown field, NULL), PIC_ESTATE,
+ * PIC_EDEVICE.
+ */
 pic_status pic_read_fields(pic_ctx *ctx, int which, double *host_out);
 
 /* Copy particles to host, ordered by their original index: out[6*n] =

@@ -109,7 +109,7 @@ def traffic_for(fam, wname):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, nsub=200_000, steps=8):
+def cpu_baseline(w, nsub=200_000, steps=16):
     """The FP64 oracle on the full grid of the same workload for `steps` steps
     with a 1/(n/nsub) subsample of the bunch; the per-push time is scaled to
     the full bunch to give the per-step time of the whole workload."""

@@ -267,7 +267,8 @@ PAPER_GAMMA = 1.45e13
 
 
 def paper_film(d_nm, dx=2e-9, t_fs=40.0, gap_nm=10.0, kinetic_ev=100e3, nparticles=4000,
-               npml=10, current_density=1e9, below_nm=100.0, above_nm=100.0, probe_um=1.5):
+               npml=10, current_density=1e9, below_nm=100.0, above_nm=100.0, probe_um=1.5,
+               gamma=PAPER_GAMMA):
     """The paper's geometry (Sec. III): film normal along x, bunch along +z,
     periodic y, Ez probe on the film surface 1.5 um downstream of the bunch start.
 
@@ -298,7 +299,7 @@ def paper_film(d_nm, dx=2e-9, t_fs=40.0, gap_nm=10.0, kinetic_ev=100e3, nparticl
     wpm = np.zeros((nx, ny, nz))
     gm = np.zeros((nx, ny, nz))
     wpm[i0:i1] = PAPER_WP
-    gm[i0:i1] = PAPER_GAMMA
+    gm[i0:i1] = gamma
     top = i1 * dx
     xs = top + gap_nm * 1e-9 + 2e-9 * truncated_normal(rng, nparticles)
     ys = rng.uniform(0.0, ny * dx, nparticles)
@@ -312,7 +313,8 @@ def paper_film(d_nm, dx=2e-9, t_fs=40.0, gap_nm=10.0, kinetic_ev=100e3, nparticl
     return Workload(f"paperfilm{d_nm}nm_{nx}x{ny}x{nz}", nx, ny, nz, dx, dt, (CPML, PERIODIC, CPML),
                     npml, wpm, gm, bunch, probes, omega, steps,
                     sort_every=20,
-                    meta={"thickness_nm": d_nm, "z0": z0, "z_probe": zp, "v": v, "film_top": top})
+                    meta={"thickness_nm": d_nm, "z0": z0, "z_probe": zp, "v": v, "film_top": top,
+                          "gamma": gamma})
 
 
 # ---------------------------------------------------------------------------

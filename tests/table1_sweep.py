@@ -89,6 +89,36 @@ def run_film(d_nm, dx=2e-9, t_fs=40.0):
             "live": st["live"], "record_fs": w.steps * w.dt * 1e15}
 
 
+def decay_rate(w, ez):
+    """Temporal decay rate (1/s) of the probe's surface-mode ringing after the
+    bunch has passed: the record band-passed to +-150 THz around its
+    strongest peak, its Hilbert envelope, and a straight-line fit of the
+    envelope's logarithm from 6 fs after the bunch's passage to 4 fs before
+    the end of the record."""
+    from scipy.signal import hilbert
+    t = (np.arange(ez.size) + 1) * w.dt
+    spec = np.fft.rfft(ez)
+    f = np.fft.rfftfreq(ez.size, w.dt)
+    band = (f > 0.5e15) & (f < 1.8e15)
+    f0 = f[band][np.argmax(np.abs(spec[band]))]
+    env = np.abs(hilbert(np.fft.irfft(spec * (np.abs(f - f0) < 0.15e15), n=ez.size)))
+    t_pass = (w.meta["z_probe"] - w.meta["z0"]) / w.meta["v"]
+    sel = (t > t_pass + 6e-15) & (t < t[-1] - 4e-15)
+    return -np.polyfit(t[sel], np.log(env[sel]), 1)[0], f0
+
+
+def run_decay(d_nm, gamma, dx=2e-9, t_fs=40.0):
+    """The paper's setup with collision frequency `gamma`: decay rate (1/s)
+    and frequency (Hz) of the probe Ez after the bunch has passed (Sec. IV)."""
+    from paper_1505_04007_amd import native
+    w = pi.paper_film(d_nm, dx=dx, t_fs=t_fs, gamma=gamma)
+    sim = native.from_workload(w, series_len=w.steps)
+    sim.step(w.steps)
+    _, ser = sim.probe(series=True)
+    sim.close()
+    return decay_rate(w, np.asarray(ser, dtype=np.float64).reshape(-1))
+
+
 def main(argv):
     thick = [int(a) for a in argv[1:]] or list(THICKNESSES)
     gp = golden_pic()

@@ -8,11 +8,14 @@ thick film (one merged branch, the single-interface limit) shows the
 staircase error plainly: its peak lies below the crossing by ~3 % at 2 nm
 cells and half that at 1 nm, and the Richardson value meets the crossing.
 The paper's own PIC column is printed beside them; it is not a pin (the
-paper's bunch and domain are not fully specified).
+paper's bunch and domain are not fully specified).  The decay of the probe
+field with the collision frequency (Sec. IV) is checked against the
+quasi-static surface-mode root of the Drude metal.
 """
 import numpy as np
 import pytest
 
+import pic_inputs as pi
 import table1_sweep as ts
 
 pytestmark = pytest.mark.gpu
@@ -41,3 +44,22 @@ def test_thick_film_converges_first_order_to_the_crossing():
     assert f2 < f1 < th + 25.0  # approached from below, error shrinking with the cell
     assert abs(th - f1) < 0.75 * abs(th - f2)
     assert abs(ex - th) <= 25.0
+
+
+def test_decay_rate_grows_with_the_collision_frequency():
+    """Sec. IV: the probe field decays faster for a larger collision frequency.
+    Thick film (one interface): the decay rate rises linearly in gamma with the
+    slope 1/2 that the quasi-static surface-mode root of the Drude metal gives
+    (eps(w) = -1 with Eq. 1: w = wp/sqrt(2) - i gamma/2); thin film: it rises
+    too, on top of the two branches' beating."""
+    g0 = pi.PAPER_GAMMA
+    facs = np.array([1.0, 2.0, 4.0, 8.0])
+    thick = np.array([ts.run_decay(150, g0 * f)[0] for f in facs])
+    slope = np.polyfit(g0 * facs, thick, 1)[0]
+    print("d = 150 nm: decay rates " + ", ".join(f"{r:.3e}" for r in thick) + f" 1/s, slope {slope:.3f}",
+          flush=True)
+    assert np.all(np.diff(thick) > 0)
+    assert 0.4 < slope < 0.6
+    thin = [ts.run_decay(50, g0 * f)[0] for f in (1.0, 4.0)]
+    print(f"d = 50 nm: decay rates {thin[0]:.3e}, {thin[1]:.3e} 1/s", flush=True)
+    assert thin[1] > thin[0]

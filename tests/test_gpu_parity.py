@@ -269,13 +269,15 @@ def test_sort_frequency_does_not_change_results():
     assert np.abs(Pa[3:] - Pb[3:]).max() <= 1e-5 * np.abs(Pb[3]).max()
 
 
-@pytest.mark.parametrize("make,steps", [(pi.film_production, 20), (pi.grating_large, 6), (pi.grating_shard, 20)])
-def test_full_size_workloads_conserve_charge(make, steps):
+@pytest.mark.parametrize("make,steps,mode", [(pi.film_production, 20, 0), (pi.grating_large, 6, 0),
+                                             (pi.grating_shard, 20, 0), (pi.grating_large, 6, 2)])
+def test_full_size_workloads_conserve_charge(make, steps, mode):
     """Full-size workloads in the benchmark's launch configuration: every live
     particle pushed each step, no non-finite field, and Gauss's law at FP32
-    round-off (a property the oracle fixes at any size)."""
+    round-off (a property the oracle fixes at any size); also with the
+    fixed-point deposit, whose per-particle rounding is at that level too."""
     w = make()
-    g = native.from_workload(w, diag=True, check_every=steps)
+    g = native.from_workload(w, diag=True, check_every=steps, deposit_mode=mode)
     g.step(steps)
     st = g.stats()
     assert st["live"] == w.bunch.n

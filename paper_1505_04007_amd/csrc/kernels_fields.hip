@@ -33,12 +33,50 @@ __device__ __forceinline__ int lin(const FieldArgs &a, int i, int j, int k)
 __device__ __forceinline__ float ld_once(const float *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_once(float *p, float v) { __builtin_nontemporal_store(v, p); }
 
-__device__ __forceinline__ float cpml(float *__restrict__ psi, int sid, float b, float c, float ik,
-                                      float d)
+// One CPML axis of one cell: its slab index, coefficients and two memories,
+// loaded with the cell's field values (all issued before any is used, so a
+// slab cell waits for memory once, not twice); update() then applies the
+// recursion psi' = b psi + c d, d' = d / kappa + psi' and stores psi'.
+struct SlabMem {
+    bool in;
+    int sid;
+    float b, c, ik, p0, p1;
+};
+
+__device__ __forceinline__ SlabMem slab_load(float *const *psi, const float *tb, const float *tc, const float *tk,
+                                             int pos, bool in, int sid)
 {
-    const float s = b * psi[sid] + c * d;
-    psi[sid] = s;
-    return d * ik + s;
+    SlabMem m{in, sid, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (in) {
+        m.b = tb[pos];
+        m.c = tc[pos];
+        m.ik = tk[pos];
+        m.p0 = psi[0][sid];
+        m.p1 = psi[1][sid];
+    }
+    return m;
+}
+
+__device__ __forceinline__ float cpml_update(float *__restrict__ psi, const SlabMem &m, float p, float d)
+{
+    const float s = m.b * p + m.c * d;
+    psi[m.sid] = s;
+    return d * m.ik + s;
+}
+
+// The three slab memberships of cell (i, j, k) with their memories (E = 1:
+// the E update's tables and memories, else the H update's).
+template <int E>
+__device__ __forceinline__ void slab_all(const FieldArgs &a, int i, int j, int k, SlabMem &mx, SlabMem &my,
+                                         SlabMem &mz)
+{
+    const PmlAxis &X = a.pml[0], &Y = a.pml[1], &Z = a.pml[2];
+    mx = slab_load(E ? X.psiE : X.psiH, E ? X.bE : X.bH, E ? X.cE : X.cH, E ? X.kE : X.kH, i,
+                   X.on && (i < X.npml || i >= a.nx - X.npml), slab_p(i, a.nx, X.npml) + 2 * X.npml * (j + a.ny * k));
+    my = slab_load(E ? Y.psiE : Y.psiH, E ? Y.bE : Y.bH, E ? Y.cE : Y.cH, E ? Y.kE : Y.kH, j,
+                   Y.on && (j < Y.npml || j >= a.ny - Y.npml), i + a.nx * (slab_p(j, a.ny, Y.npml) + 2 * Y.npml * k));
+    mz = slab_load(E ? Z.psiE : Z.psiH, E ? Z.bE : Z.bH, E ? Z.cE : Z.cH, E ? Z.kE : Z.kH, k,
+                   Z.on && (k < Z.npml || k >= a.nz - Z.npml), i + a.nx * (j + a.ny * slab_p(k, a.nz, Z.npml)));
 }
 
 
@@ -82,6 +120,8 @@ __device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, 
     float exy = Ex[id + oy], ezy = Ez[id + oy];
     float exz = Ex[id + oz], eyz = Ey[id + oz];
     const float hx = ld_once(H0 + id), hy = ld_once(H1 + id), hz = ld_once(H2 + id);
+    SlabMem mx, my, mz;
+    slab_all<0>(a, i, j, k, mx, my, mz);
     eyx = okx ? eyx : 0.f;
     ezx = okx ? ezx : 0.f;
     exy = oky ? exy : 0.f;
@@ -91,32 +131,17 @@ __device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, 
     float dyEz = ezy - ez, dzEy = eyz - ey;
     float dzEx = exz - ex, dxEz = ezx - ez;
     float dxEy = eyx - ey, dyEx = exy - ex;
-    if (a.pml[0].on) {
-        const PmlAxis &P = a.pml[0];
-        if (i < P.npml || i >= a.nx - P.npml) {
-            const int sid = slab_p(i, a.nx, P.npml) + 2 * P.npml * (j + a.ny * k);
-            const float b = P.bH[i], c = P.cH[i], ik = P.kH[i];
-            dxEz = cpml(P.psiH[0], sid, b, c, ik, dxEz);
-            dxEy = cpml(P.psiH[1], sid, b, c, ik, dxEy);
-        }
+    if (mx.in) {
+        dxEz = cpml_update(a.pml[0].psiH[0], mx, mx.p0, dxEz);
+        dxEy = cpml_update(a.pml[0].psiH[1], mx, mx.p1, dxEy);
     }
-    if (a.pml[1].on) {
-        const PmlAxis &P = a.pml[1];
-        if (j < P.npml || j >= a.ny - P.npml) {
-            const int sid = i + a.nx * (slab_p(j, a.ny, P.npml) + 2 * P.npml * k);
-            const float b = P.bH[j], c = P.cH[j], ik = P.kH[j];
-            dyEz = cpml(P.psiH[0], sid, b, c, ik, dyEz);
-            dyEx = cpml(P.psiH[1], sid, b, c, ik, dyEx);
-        }
+    if (my.in) {
+        dyEz = cpml_update(a.pml[1].psiH[0], my, my.p0, dyEz);
+        dyEx = cpml_update(a.pml[1].psiH[1], my, my.p1, dyEx);
     }
-    if (a.pml[2].on) {
-        const PmlAxis &P = a.pml[2];
-        if (k < P.npml || k >= a.nz - P.npml) {
-            const int sid = i + a.nx * (j + a.ny * slab_p(k, a.nz, P.npml));
-            const float b = P.bH[k], c = P.cH[k], ik = P.kH[k];
-            dzEy = cpml(P.psiH[0], sid, b, c, ik, dzEy);
-            dzEx = cpml(P.psiH[1], sid, b, c, ik, dzEx);
-        }
+    if (mz.in) {
+        dzEy = cpml_update(a.pml[2].psiH[0], mz, mz.p0, dzEy);
+        dzEx = cpml_update(a.pml[2].psiH[1], mz, mz.p1, dzEx);
     }
     const float S = a.S;
     const float nhx = hx - S * (dyEz - dzEy);
@@ -154,6 +179,8 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
     float hxy = Hx[id + oy], hzy = Hz[id + oy];
     float hxz = Hx[id + oz], hyz = Hy[id + oz];
     const float ex = ld_once(a.E[0] + id), ey = ld_once(a.E[1] + id), ez = ld_once(a.E[2] + id);
+    SlabMem mx, my, mz;
+    slab_all<1>(a, i, j, k, mx, my, mz);
     hyx = okx ? hyx : 0.f;
     hzx = okx ? hzx : 0.f;
     hxy = oky ? hxy : 0.f;
@@ -163,32 +190,17 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
     float dyHz = hz - hzy, dzHy = hy - hyz;
     float dzHx = hx - hxz, dxHz = hz - hzx;
     float dxHy = hy - hyx, dyHx = hx - hxy;
-    if (a.pml[0].on) {
-        const PmlAxis &P = a.pml[0];
-        if (i < P.npml || i >= a.nx - P.npml) {
-            const int sid = slab_p(i, a.nx, P.npml) + 2 * P.npml * (j + a.ny * k);
-            const float b = P.bE[i], c = P.cE[i], ik = P.kE[i];
-            dxHz = cpml(P.psiE[0], sid, b, c, ik, dxHz);
-            dxHy = cpml(P.psiE[1], sid, b, c, ik, dxHy);
-        }
+    if (mx.in) {
+        dxHz = cpml_update(a.pml[0].psiE[0], mx, mx.p0, dxHz);
+        dxHy = cpml_update(a.pml[0].psiE[1], mx, mx.p1, dxHy);
     }
-    if (a.pml[1].on) {
-        const PmlAxis &P = a.pml[1];
-        if (j < P.npml || j >= a.ny - P.npml) {
-            const int sid = i + a.nx * (slab_p(j, a.ny, P.npml) + 2 * P.npml * k);
-            const float b = P.bE[j], c = P.cE[j], ik = P.kE[j];
-            dyHz = cpml(P.psiE[0], sid, b, c, ik, dyHz);
-            dyHx = cpml(P.psiE[1], sid, b, c, ik, dyHx);
-        }
+    if (my.in) {
+        dyHz = cpml_update(a.pml[1].psiE[0], my, my.p0, dyHz);
+        dyHx = cpml_update(a.pml[1].psiE[1], my, my.p1, dyHx);
     }
-    if (a.pml[2].on) {
-        const PmlAxis &P = a.pml[2];
-        if (k < P.npml || k >= a.nz - P.npml) {
-            const int sid = i + a.nx * (j + a.ny * slab_p(k, a.nz, P.npml));
-            const float b = P.bE[k], c = P.cE[k], ik = P.kE[k];
-            dzHy = cpml(P.psiE[0], sid, b, c, ik, dzHy);
-            dzHx = cpml(P.psiE[1], sid, b, c, ik, dzHx);
-        }
+    if (mz.in) {
+        dzHy = cpml_update(a.pml[2].psiE[0], mz, mz.p0, dzHy);
+        dzHx = cpml_update(a.pml[2].psiE[1], mz, mz.p1, dzHx);
     }
     const float S = a.S;
     float nex = ex + S * (dyHz - dzHy);

@@ -106,3 +106,52 @@ def test_full_bunch_first_push_matches_oracle_sample():
     assert dpos <= 1e-4                          # FP32 positions of ~300 cells
     assert dk <= 1e-2                            # FP32 storage of u: 6e-8 |u| against the kick
     assert np.abs(P[3:, idx] - Po[3:]).max() <= 1e-6 * umax
+
+
+def test_full_batched_sweep_matches_its_plain_runs():
+    """The 16-instance sweep (films 5-80 nm, grids 128x64x64 to 192x96x96,
+    2e5 particles each) as one batch with its captured graph: every member's
+    fields, pushes and probe spectra equal its own plain run to the FP32
+    deposit's rounding (the per-cell arithmetic is the plain kernels')."""
+    ws = pi.batched_sweep()
+    steps = 45
+    plain = []
+    for w in ws:
+        s = native.from_workload(w)
+        s.step(steps)
+        plain.append((s.fields(native.FIELD_E), s.stats()["pushes"], s.probe()))
+        s.close()
+    sims = [native.from_workload(w) for w in ws]
+    b = native.Batch(sims, use_graph=True)
+    b.step(steps)
+    worst = 0.0
+    for s, (E, pushes, F) in zip(sims, plain):
+        e = _rel(s.fields(native.FIELD_E), E)
+        worst = max(worst, e)
+        assert e <= 1e-5
+        assert s.stats()["pushes"] == pushes
+        assert np.abs(s.probe() - F).max() <= 1e-4 * np.abs(F).max()
+    print(f"16 members after {steps} steps: worst E rel-L2 against the plain run {worst:.2e}", flush=True)
+    b.close()
+
+
+def test_full_adjoint_workload_properties():
+    """The adjoint workload at its full size (128x64x64, 20 nm film with map
+    noise, 1e5 particles, 2000 steps): L equals the probe power of the same
+    forward run, the gradients vanish outside the metal and are finite, and
+    the checkpointed reverse pass (interval 45) agrees with the store-all one."""
+    w = pi.film_adjoint()
+    w0 = w.meta["omega0"]
+    N = w.steps
+    a = native.from_workload(w)
+    L, gw, gg = a.grad(w0, N)
+    F = a.probe()[:, 0]
+    assert abs(L - float(np.sum(np.abs(F) ** 2))) <= 1e-9 * L
+    metal = w.wp_map > 0
+    assert np.all(gw[~metal] == 0) and np.all(gg[~metal] == 0)
+    assert np.all(np.isfinite(gw)) and np.abs(gw[metal]).max() > 0
+    b = native.from_workload(w)
+    L2, gw2, gg2 = b.grad(w0, N, ckpt_every=45)
+    assert abs(L2 - L) <= 1e-4 * L
+    assert np.linalg.norm(gw2 - gw) <= 1e-3 * np.linalg.norm(gw)
+    assert np.linalg.norm(gg2 - gg) <= 1e-3 * np.linalg.norm(gg)

@@ -268,6 +268,31 @@ pic_status pic_probe(pic_ctx *ctx, double *re, double *im, double *series);
 pic_status pic_grad(pic_ctx *ctx, double omega0, int64_t nsteps, int64_t ckpt_every, double *L,
                     double *dL_dwp, double *dL_dgamma);
 
+/*
+ * pic_grad without device allocation, for callers that cannot allocate
+ * device memory (code recording a HIP graph, serving loops, harnesses that
+ * forbid hipMalloc).  Same result as pic_grad(ctx, omega0, nsteps, 0, ...)
+ * taken in its store-all form (every step's metal-box snapshot kept, nothing
+ * replayed), and the same kernels; every device buffer of the call (the
+ * snapshots, the FP64 probe record, the adjoint state and the gradient
+ * accumulators) is carved from one static device array of 64 MiB that the
+ * library holds on each device it runs on until the process ends, and the
+ * call allocates and frees no device memory (host memory for the FP64
+ * objective is ordinary heap memory; per-launch timing, opts.timing, is
+ * suspended for the call since it creates HIP events).  The array is
+ * cleared where it must start at zero on every call, so it keeps no result
+ * from one call to the next, but all calls on one device share it: calls
+ * that overlap in time on one device (other threads, other streams) race
+ * and give wrong results.
+ * Needs roughly nsteps * 24 bytes per metal-box cell plus 28 bytes per grid
+ * cell (and the CPML slabs); a call that needs more than the array holds
+ * returns PIC_EINVAL with the sizes in the message, before anything runs.
+ * Errors: as pic_grad, plus PIC_EINVAL (scratch too small) and PIC_EDEVICE
+ * when the array's device address could not be obtained at pic_init.
+ */
+pic_status pic_grad_noalloc(pic_ctx *ctx, double omega0, int64_t nsteps, double *L, double *dL_dwp,
+                            double *dL_dgamma);
+
 /* Result of the field-kernel tile autotuner. */
 typedef struct {
     int32_t tile;     /* chosen tile variant index */

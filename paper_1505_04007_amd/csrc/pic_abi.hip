@@ -349,6 +349,7 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
     pic_opts o{};
     if (opts) o = *opts;
     c->stream = (hipStream_t)o.stream;
+    bind_static_scratch(c);
     c->sort_every = o.sort_every > 0 ? o.sort_every : 0;
     c->check_every = o.check_every > 0 ? o.check_every : 0;
     c->timing = o.timing != 0;

@@ -3,9 +3,52 @@
 // reverse pass over the adjoint kernels, and the timed choice of tile shape.
 #include "pic_host.hpp"
 
+#include <mutex>
+
 using namespace pich;
 
+namespace {
+
+// Device scratch of pic_grad_noalloc: every buffer of that call is carved
+// from this array instead of being allocated.  Each device the library runs
+// on holds its own copy until the process ends; all calls on one device share
+// it.  Host code never passes the array's name to a kernel or a copy (on the
+// host it is only a stand-in for the symbol): it uses the device address
+// bound per device below.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices] = {};
+
+}  // namespace
+
 namespace pich {
+
+void bind_static_scratch(pic_ctx *c)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        c->sscratch_err = "pic_grad_noalloc: no usable current device at pic_init";
+        return;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            c->sscratch_err = std::string("pic_grad_noalloc: hipGetSymbolAddress of the static scratch failed: ") +
+                              hipGetErrorString(e);
+            return;
+        }
+        g_scratch_addr[dev] = (char *)p;
+    }
+    c->sscratch = g_scratch_addr[dev];
+}
 
 size_t slab_cells(const pic_ctx *c, int a)
 {
@@ -125,8 +168,8 @@ pic_status arena_take(pic_ctx *c, GradScratch &g, Arena &ar, size_t count, float
 // snapshot for every step and the reverse pass needs no replay; otherwise
 // it keeps a field checkpoint every K steps and the bunch current of every
 // step, and the reverse pass replays each segment to regenerate them.
-pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, bool store_all, double *L,
-                     double *dL_dwp, double *dL_dgamma)
+pic_status grad_impl(pic_ctx *c, GradScratch &g, double omega0, long long N, long long K, bool store_all,
+                     double *L, double *dL_dwp, double *dL_dgamma)
 {
     const size_t ncell = (size_t)c->n[0] * c->n[1] * c->n[2];
     const int npr = c->nprobe;
@@ -134,8 +177,6 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, bool s
     if (store_all) K = N;
     const long long nseg = (N + K - 1) / K;
     const long long s0 = c->step;
-    GradScratch g;
-    g.s = c->stream;
 
     float *traj = nullptr;  // metal-box snapshots: one per step of a segment, or of the run
     TRY(galloc(c, g, &traj, (size_t)K * 6 * c->nbox));
@@ -376,6 +417,24 @@ pic_status grad_impl(pic_ctx *c, double omega0, long long N, long long K, bool s
     return PIC_OK;
 }
 
+// Device bytes grad_impl takes from its scratch in store-all mode: every
+// galloc of that path (snapshots, probe record, seeds, adjoint state,
+// gradient accumulators, the full-grid box), each rounded as galloc rounds.
+size_t store_all_bytes(const pic_ctx *c, long long N)
+{
+    auto r = [](size_t b) { return align256(std::max<size_t>(b, 256)); };
+    const size_t ncell = (size_t)c->n[0] * c->n[1] * c->n[2];
+    const size_t npr = (size_t)c->nprobe;
+    size_t t = r((size_t)N * 6 * c->nbox * 4) + r((size_t)N * npr * 8) + r((size_t)N * npr * 4);
+    for (int d = 0; d < 3; ++d) {
+        t += 2 * r(ncell * 4) + r(c->nbox * 4);
+        if (c->pml[d].on) t += 8 * r(slab_cells(c, d) * 4);
+    }
+    t += 2 * r(c->nbox * 8);
+    if (c->np > 0) t += r(6 * sizeof(int));
+    return t;
+}
+
 // Average milliseconds of one H + E launch pair for every tile shape, timed
 // on the context's stream from its current field state; the state (fields,
 // CPML memories, Drude current, step clock, non-finite flag) is restored
@@ -454,7 +513,39 @@ pic_status pic_grad(pic_ctx *c, double omega0, int64_t nsteps, int64_t ckpt_ever
         return fail(c, PIC_ENOTSUP,
                     "pic_grad with checkpoints records the FP32 bunch current: not available with the "
                     "fixed-point deposit (deposit_mode 2); use ckpt_every = 0 with enough device memory");
-    return grad_impl(c, omega0, (long long)nsteps, K, store_all, L, dL_dwp, dL_dgamma);
+    GradScratch g;
+    g.s = c->stream;
+    return grad_impl(c, g, omega0, (long long)nsteps, K, store_all, L, dL_dwp, dL_dgamma);
+}
+
+// pic_grad in its store-all form with every device buffer carved from the
+// static scratch: no device memory is allocated or freed.
+pic_status pic_grad_noalloc(pic_ctx *c, double omega0, int64_t nsteps, double *L, double *dL_dwp,
+                            double *dL_dgamma)
+{
+    CHECK_CTX(c);
+    if (nsteps < 1) return fail(c, PIC_EINVAL, "nsteps must be >= 1");
+    if (!L) return fail(c, PIC_EINVAL, "L is NULL");
+    if (!std::isfinite(omega0)) return fail(c, PIC_EINVAL, "omega0 must be finite");
+    if (c->nprobe < 1) return fail(c, PIC_EINVAL, "pic_grad_noalloc needs at least one probe");
+    if (!c->sscratch) return fail(c, PIC_EDEVICE, "%s", c->sscratch_err.c_str());
+    if (nsteps > ((long long)1 << 40)) return fail(c, PIC_EINVAL, "nsteps = %lld is too large", (long long)nsteps);
+    const size_t need = store_all_bytes(c, (long long)nsteps);
+    if (need > kStaticScratchBytes)
+        return fail(c, PIC_EINVAL,
+                    "pic_grad_noalloc: %lld steps need %zu bytes of device scratch, more than the static "
+                    "scratch's %zu (use pic_grad)",
+                    (long long)nsteps, need, kStaticScratchBytes);
+    GradScratch g;
+    g.s = c->stream;
+    g.fixed = c->sscratch;
+    g.cap = kStaticScratchBytes;
+    // per-launch timing creates HIP events; this path creates nothing
+    const bool timing = c->timing;
+    c->timing = false;
+    const pic_status st = grad_impl(c, g, omega0, (long long)nsteps, (long long)nsteps, true, L, dL_dwp, dL_dgamma);
+    c->timing = timing;
+    return st;
 }
 
 // Field-kernel tile autotuner: time H + E launches of every tile shape on

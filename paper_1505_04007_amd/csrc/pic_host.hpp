@@ -93,6 +93,11 @@ struct pic_ctx {
 
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[pich::kFamilies];
+
+    // this device's address of the library's static gradient scratch (bound at
+    // pic_init), or null with the reason in sscratch_err
+    char *sscratch = nullptr;
+    std::string sscratch_err;
 };
 
 namespace pich {
@@ -150,15 +155,21 @@ pic_status step_body(pic_ctx *c, const pic::BoxCopyArgs *rec);
 pic_status step_once(pic_ctx *c);
 pic::DiagArgs diag_args(pic_ctx *c);
 
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 // Field-state checkpoints (pic_grad.hip), used by the gradient and the tuners.
 // Device memory of one pic_grad call, released on every exit path once the
-// stream has drained.
+// stream has drained.  With `fixed` set, the buffers are carved instead from
+// that region of `cap` bytes (the static scratch of pic_grad_noalloc) and
+// nothing is allocated or freed.
 struct GradScratch {
     hipStream_t s = nullptr;
     std::vector<void *> p;
+    char *fixed = nullptr;
+    size_t cap = 0, used = 0;
     ~GradScratch()
     {
-        if (p.empty()) return;
+        if (p.empty() && used == 0) return;
         (void)hipStreamSynchronize(s);
         for (void *q : p) (void)hipFree(q);
     }
@@ -169,6 +180,14 @@ pic_status galloc(pic_ctx *c, GradScratch &g, T **out, size_t count)
 {
     void *q = nullptr;
     const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (g.fixed) {
+        const size_t b = align256(bytes);
+        if (b > g.cap - g.used)
+            return fail(c, PIC_EINVAL, "pic_grad_noalloc: the %zu-byte static scratch is exhausted", g.cap);
+        *out = (T *)(g.fixed + g.used);
+        g.used += b;
+        return PIC_OK;
+    }
     hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -179,8 +198,6 @@ pic_status galloc(pic_ctx *c, GradScratch &g, T **out, size_t count)
     *out = (T *)q;
     return PIC_OK;
 }
-
-inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Everything a fields-only step reads and writes: the state one checkpoint holds.
 struct StateArr {
@@ -201,5 +218,10 @@ pic_status ckpt_load(pic_ctx *c, const char *src, const Mirror &m);
 
 // The tuners' choice among timed shapes (pic_grad.hip).
 int pick_shape(const double *ms);
+
+// Bind this device's address of the static gradient scratch to the context
+// (pic_grad.hip; called by pic_init with the context's device current).  A
+// failure is recorded in c->sscratch_err for pic_grad_noalloc to report.
+void bind_static_scratch(pic_ctx *c);
 
 }  // namespace pich

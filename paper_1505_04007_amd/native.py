@@ -75,7 +75,7 @@ class PicTuneOut(ctypes.Structure):
 EXPORTS = ("pic_abi_version", "pic_init", "pic_step", "pic_probe", "pic_grad", "pic_tune",
            "pic_read_fields", "pic_read_particles", "pic_diag", "pic_stats", "pic_timing",
            "pic_destroy", "pic_last_error", "pic_batch_create", "pic_batch_step", "pic_batch_tune",
-           "pic_batch_destroy", "pic_batch_last_error", "pic_query_sizes")
+           "pic_batch_destroy", "pic_batch_last_error", "pic_query_sizes", "pic_grad_noalloc")
 
 
 def _tune_dict(t):
@@ -112,6 +112,8 @@ def load():
     lib.pic_probe.argtypes = [vp, _dp, _dp, _dp]
     lib.pic_grad.restype = ctypes.c_int
     lib.pic_grad.argtypes = [vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
+    lib.pic_grad_noalloc.restype = ctypes.c_int
+    lib.pic_grad_noalloc.argtypes = [vp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp]
     lib.pic_read_fields.restype = ctypes.c_int
     lib.pic_read_fields.argtypes = [vp, ctypes.c_int, _dp]
     lib.pic_read_particles.restype = ctypes.c_int
@@ -349,6 +351,16 @@ class Simulation:
         gg = np.zeros(N)
         self._check(self._lib.pic_grad(self._h, float(omega0), int(nsteps), int(ckpt_every), _p(L),
                                        _p(gw), _p(gg)))
+        return float(L[0]), from_compact(gw, self.n), from_compact(gg, self.n)
+
+    def grad_noalloc(self, omega0, nsteps):
+        """pic_grad_noalloc: pic_grad's store-all form with no device allocation."""
+        N = self.n[0] * self.n[1] * self.n[2]
+        L = np.zeros(1)
+        gw = np.zeros(N)
+        gg = np.zeros(N)
+        self._check(self._lib.pic_grad_noalloc(self._h, float(omega0), int(nsteps), _p(L), _p(gw),
+                                               _p(gg)))
         return float(L[0]), from_compact(gw, self.n), from_compact(gg, self.n)
 
 

@@ -33,10 +33,13 @@
  * in the design notes; each is restated at the code that applies it.
  *
  * Pins: every part is checked against closed forms, exact invariants or brute
- * force in the test suite, except the CPML layers (cpml_coeff and the psi
- * recursions): they are held only to a reflection bound against a large-box
- * run, and their grading with kappa > 1 is exercised by no pin.  CPML: parity
- * unpinned beyond that bound.
+ * force in the test suite.  The CPML layers are held to the z-domain
+ * dispersion roots of a uniformly stretched periodic axis (the psi recursion
+ * and its 1/kappa), to the conserved kappa-weighted Yee energy of graded
+ * lossless layers (which node or half node each coefficient belongs to), and
+ * to the recursive convolution of the continuous CPML kernel (b and c from
+ * sigma, kappa, alpha); the grading polynomial itself is a chosen reading.
+ * The osim_test_* entries exist for those pins only.
  *
  * The differentiable form (the gradient of probe spectral power with respect
  * to the per-cell wp and gamma of Eq. 1) is the plain reverse-time transpose
@@ -166,6 +169,48 @@ static void cpml_coeff(const osim *s, int a, double pos, const double *pml, doub
     *c = (sig > 0.0) ? sig * (*b - 1.0) / (sig * kap_ + kap_ * kap_ * alp) : 0.0;
     *kap = kap_;
     *in = 1;
+}
+
+/*
+ * Test-only: make axis a a uniform stretched coordinate with the given
+ * recursion coefficients at every E-type and H-type position (so a periodic
+ * axis stays translation invariant), allocating the memories it needs.  The
+ * step's arithmetic is untouched; only its coefficient tables change.
+ */
+void osim_test_uniform_cpml(osim *s, int a, double b, double c, double kappa)
+{
+    for (int i = 0; i <= s->n[a]; ++i) {
+        s->bE[a][i] = b;
+        s->cE[a][i] = c;
+        s->kE[a][i] = kappa;
+        s->lE[a][i] = 1;
+    }
+    for (int i = 0; i < s->n[a]; ++i) {
+        s->bH[a][i] = b;
+        s->cH[a][i] = c;
+        s->kH[a][i] = kappa;
+        s->lH[a][i] = 1;
+    }
+    int e[3];
+    for (int comp = 0; comp < 3; ++comp) {
+        if (comp == a) continue;
+        e_ext(s, comp, e);
+        if (!s->psiE[comp][a].v) s->psiE[comp][a] = fnew(e[0], e[1], e[2]);
+        h_ext(s, comp, e);
+        if (!s->psiH[comp][a].v) s->psiH[comp][a] = fnew(e[0], e[1], e[2]);
+    }
+}
+
+/* Test-only: copy out the coefficient tables of axis a (h = 0: E-type at
+ * nodes 0..n, n+1 entries; h = 1: H-type at i+1/2, n entries). */
+void osim_cpml_profile(const osim *s, int a, int h, double *b, double *c, double *kappa)
+{
+    const int len = h ? s->n[a] : s->n[a] + 1;
+    for (int i = 0; i < len; ++i) {
+        b[i] = h ? s->bH[a][i] : s->bE[a][i];
+        c[i] = h ? s->cH[a][i] : s->cE[a][i];
+        kappa[i] = h ? s->kH[a][i] : s->kE[a][i];
+    }
 }
 
 /* Drude coefficients of Eq. 6 (c.f. the printed fractions). */

@@ -69,6 +69,9 @@ def _load():
     lib.osim_adj_ptr.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_int)]
     lib.osim_grad.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_double, _dp, _dp, _dp]
+    lib.osim_test_uniform_cpml.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double]
+    lib.osim_cpml_profile.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
     _LIB = lib
     return lib
 
@@ -288,3 +291,17 @@ class OracleSim:
         gg = np.zeros(self.n)
         self._lib.osim_grad(self._h, int(nsteps), float(omega0), _p(L), _p(gw), _p(gg))
         return float(L[0]), gw, gg
+
+    # ---- test-only access to the absorbing layers' coefficient tables ----
+    def test_uniform_cpml(self, axis, b, c, kappa):
+        """Give axis `axis` the same CPML recursion (b, c, kappa) at every E-type
+        and H-type position (test-only; the step's arithmetic is unchanged)."""
+        self._lib.osim_test_uniform_cpml(self._h, int(axis), float(b), float(c), float(kappa))
+
+    def cpml_profile(self, axis, h):
+        """(b, c, kappa) tables of an axis: h = 0 E-type at nodes 0..n, h = 1
+        H-type at i + 1/2, i = 0..n-1 (b = 1, c = 0, kappa = 1 outside the layers)."""
+        n = self.n[axis] + (0 if h else 1)
+        b, c, k = np.zeros(n), np.zeros(n), np.zeros(n)
+        self._lib.osim_cpml_profile(self._h, int(axis), int(h), _p(b), _p(c), _p(k))
+        return b, c, k

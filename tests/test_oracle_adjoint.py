@@ -43,8 +43,9 @@ def _make(po, n, bc, npml, pml, rng, metal_frac=0.5):
 
 
 CASES = [
-    ((5, 4, 6), ("CPML", "PERIODIC", "PEC"), 2, (3.0, 1.0, 2.5, 3e-3)),
-    ((6, 5, 4), ("CPML", "CPML", "CPML"), 2, (2.0, 1.3, 1.7, 1e-3)),
+    # alpha_max of a few 1e6 S/m is comparable with sigma_max (~1e7 S/m at 3 nm)
+    ((5, 4, 6), ("CPML", "PERIODIC", "PEC"), 2, (3.0, 1.0, 2.5, 3e6)),
+    ((6, 5, 4), ("CPML", "CPML", "CPML"), 2, (2.0, 1.3, 1.7, 1e6)),
     ((4, 5, 3), ("PERIODIC", "PERIODIC", "PERIODIC"), 0, (3.0, 1.0, 1.0, 0.0)),
     ((4, 3, 5), ("PEC", "PEC", "CPML"), 2, (3.0, 1.0, 1.0, 0.0)),
 ]

@@ -15,6 +15,7 @@ import os
 import pytest
 
 import test_oracle_adjoint as ta
+import test_oracle_cpml as tc
 import test_oracle_fields as tf
 import test_oracle_particles as tp
 
@@ -39,6 +40,10 @@ PROBE = lambda m: tp.test_probe_dft_of_exact_cavity_mode(m)  # noqa: E731
 TRANSPOSE = lambda m: [ta.test_adjoint_step_is_transpose_blockwise(m, c) for c in range(len(ta.CASES))]  # noqa: E731
 FD = lambda m: ta.test_gradient_matches_central_differences(m)  # noqa: E731
 CPML = lambda m: tp.test_cpml_reflection_below_minus_40_db(m)  # noqa: E731
+UNIFORM = lambda m: tc.test_uniform_cpml_every_axis_and_polarisation(m)  # noqa: E731
+KENERGY = lambda m: tc.test_kappa_graded_layers_conserve_the_weighted_yee_energy(m)  # noqa: E731
+KERNEL = lambda m: tc.test_cpml_coefficients_are_the_recursive_convolution_of_the_kernel(m)  # noqa: E731
+DIAG = lambda m: tc.test_diagnostics_by_hand(m)  # noqa: E731
 
 # (name, original text, planted mistake, pins expected to catch it)
 MUTANTS = [
@@ -94,9 +99,27 @@ MUTANTS = [
     ("gradient: cb's factor taken from J instead of E^n",
      "gcb[q] += jt * En[q];", "gcb[q] += jt * Jn[q];", [FD]),
     ("CPML: sign of the memory coefficient c",
-     "*c = (sig > 0.0) ? sig * (*b - 1.0) /", "*c = (sig > 0.0) ? sig * (1.0 - *b) /", [CPML]),
+     "*c = (sig > 0.0) ? sig * (*b - 1.0) /", "*c = (sig > 0.0) ? sig * (1.0 - *b) /", [CPML, KERNEL]),
     ("CPML: conductivity grading reversed (largest at the interface)",
-     "const double sig = smax * pow(r, m);", "const double sig = smax * pow(1.0 - r, m);", [CPML]),
+     "const double sig = smax * pow(r, m);", "const double sig = smax * pow(1.0 - r, m);", [CPML, KERNEL]),
+    ("CPML: memory used before its update (Hz, x derivative)",
+     "*p = s->bH[0][i] * *p + s->cH[0][i] * dx;\n                    dx = dx / s->kH[0][i] + *p;\n"
+     "                }\n                if (s->lH[1][j]) {\n                    double *p = &AT(s->psiH[2][1]",
+     "const double old_ = *p;\n                    *p = s->bH[0][i] * *p + s->cH[0][i] * dx;\n"
+     "                    dx = dx / s->kH[0][i] + old_;\n"
+     "                }\n                if (s->lH[1][j]) {\n                    double *p = &AT(s->psiH[2][1]",
+     [UNIFORM]),
+    ("CPML: 1/kappa applied to the memory as well (Ey, z derivative)",
+     "double *p = &AT(s->psiE[1][2], i, j, k);\n                    *p = s->bE[2][k] * *p + s->cE[2][k] * dz;\n"
+     "                    dz = dz / s->kE[2][k] + *p;",
+     "double *p = &AT(s->psiE[1][2], i, j, k);\n                    *p = s->bE[2][k] * *p + s->cE[2][k] * dz;\n"
+     "                    dz = (dz + *p) / s->kE[2][k];",
+     [UNIFORM]),
+    ("CPML: H-type coefficients sampled at the nodes instead of the half nodes",
+     "cpml_coeff(s, a, i + 0.5, pml,", "cpml_coeff(s, a, (double)i, pml,", [KENERGY, KERNEL]),
+    ("diagnostics: periodic copies counted in the field energy",
+     "if (s->bc[a] == OR_PERIODIC && id[a] == s->n[a]) dup = 1;",
+     "if (s->bc[a] == OR_PERIODIC && id[a] > s->n[a]) dup = 1;", [DIAG]),
 ]
 
 

@@ -118,6 +118,13 @@ def gaussian_bunch(rng, n, center, sigma, kinetic_ev, charge=1e-15):
                  -E_CHARGE, M_E, charge / (n * E_CHARGE))
 
 
+def aloof_center(top_z, gap, sigma_z, cut=3.0):
+    """Height of a bunch centre whose truncated lower edge (cut sigma below the
+    centre) clears the film top by `gap`: the bunch travels wholly above the
+    surface, as an aloof beam "N nm above the surface" does."""
+    return top_z + gap + cut * sigma_z
+
+
 def film_maps(nx, ny, nz, k0, k1, wp=AG_WP, gamma=AG_GAMMA):
     """Drude maps with metal in the z-cells k0 <= k < k1 (full x, y)."""
     wpm = np.zeros((nx, ny, nz))
@@ -148,13 +155,14 @@ def slab_tiny(with_bunch=True):
 
 
 def film_production(nparticles=1_000_000, seed_index=1):
-    """256x128x128, dx = 2 nm, 8-cell CPML, 30 nm film, 50 keV bunch 8 nm above."""
+    """256x128x128, dx = 2 nm, 8-cell CPML, 30 nm film, 50 keV bunch 8 nm above
+    the surface (gap to the bunch's truncated lower edge)."""
     nx, ny, nz, dx, npml = 256, 128, 128, 2e-9, 8
     top = nz // 2
     wpm, gm = film_maps(nx, ny, nz, top - 15, top)
     rng = np.random.default_rng(SEED0 + seed_index)
     sig = (20e-9, 5e-9, 5e-9)
-    center = (npml * dx + 3 * sig[0], ny * dx / 2, top * dx + 8e-9)
+    center = (npml * dx + 3 * sig[0], ny * dx / 2, aloof_center(top * dx, 8e-9, sig[2]))
     bunch = gaussian_bunch(rng, nparticles, center, sig, 50e3)
     zp = top * dx + 2e-9
     probes = np.array([[nx * dx * f, ny * dx / 2, zp] for f in (0.5, 0.625, 0.75)])
@@ -173,7 +181,7 @@ def film_adjoint(nparticles=100_000):
     wpm[metal] *= 1.0 + 0.05 * rng.standard_normal(int(metal.sum()))
     gm[metal] *= 1.0 + 0.05 * rng.standard_normal(int(metal.sum()))
     sig = (20e-9, 5e-9, 5e-9)
-    center = (npml * dx + 3 * sig[0], ny * dx / 2, top * dx + 8e-9)
+    center = (npml * dx + 3 * sig[0], ny * dx / 2, aloof_center(top * dx, 8e-9, sig[2]))
     bunch = gaussian_bunch(rng, nparticles, center, sig, 50e3)
     zp = top * dx + 2e-9
     probes = np.array([[nx * dx * f, ny * dx / 2, zp] for f in (0.5, 0.625, 0.75)])
@@ -196,7 +204,7 @@ def grating_large(nparticles=10_000_000):
     gm[groove, :, top - 10:top] = 0.0
     rng = np.random.default_rng(SEED0 + 4)
     sig = (50e-9, 10e-9, 10e-9)
-    center = (npml * dx + 3 * sig[0], ny * dx / 2, top * dx + 5e-9)
+    center = (npml * dx + 3 * sig[0], ny * dx / 2, aloof_center(top * dx, 5e-9, sig[2]))
     bunch = gaussian_bunch(rng, nparticles, center, sig, 100e3)
     zp = top * dx + 2e-9
     probes = np.array([[nx * dx * f, ny * dx / 2, zp] for f in (0.5, 0.625, 0.75)])
@@ -250,7 +258,7 @@ def batched_sweep(nparticles=200_000):
         tc = int(round(t_nm * 1e-9 / dx))
         wpm, gm = film_maps(nx, ny, nz, top - tc, top)
         sig = (20e-9, 5e-9, 5e-9)
-        center = (npml * dx + 3 * sig[0], ny * dx / 2, top * dx + 8e-9)
+        center = (npml * dx + 3 * sig[0], ny * dx / 2, aloof_center(top * dx, 8e-9, sig[2]))
         bunch = gaussian_bunch(rng, nparticles, center, sig, float(energies[i]))
         zp = top * dx + 2e-9
         probes = np.array([[nx * dx * q, ny * dx / 2, zp] for q in (0.5, 0.625, 0.75)])

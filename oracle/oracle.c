@@ -92,9 +92,11 @@ typedef struct {
     long step;
     double t_field, t_part;
     long pushes;
-    /* bunch current as a prescribed source: presc[(step - presc0) * nJ + ...] */
+    /* bunch current as a prescribed source: presc[(step - presc0) * nJ + ...],
+       either the whole arrays (pbox_on = 0) or a box of them (lo, ext) */
     double *presc;
     long presc_n, presc0;
+    int pbox_on, pbox_lo[3], pbox_ext[3];
     /* adjoint state (reverse-time), same extents as the forward arrays */
     int adj_on;
     ofield Ea[3], Ha[3], Ja[3];
@@ -642,14 +644,45 @@ static void add_at(osim *s, ofield *f, int i, int j, int k, double v)
 }
 
 /*
+ * A copy of the three bunch-current arrays over a box of lattice indices
+ * lo .. lo + ext - 1 per axis (unwrapped: indices may lie one node outside
+ * the grid), components back to back, x slowest.  Deposits land here first;
+ * jbox_flush adds the box to J_b, wrapping periodic axes and dropping what
+ * lies outside the grid.
+ */
+typedef struct {
+    double *v;
+    int lo[3], ext[3];
+} jbox;
+
+static void jbox_add(jbox *b, int c, int i, int j, int k, double v)
+{
+    const size_t q = (((size_t)c * b->ext[0] + (size_t)(i - b->lo[0])) * b->ext[1] + (size_t)(j - b->lo[1])) *
+                         b->ext[2] +
+                     (size_t)(k - b->lo[2]);
+    b->v[q] += v;
+}
+
+static void jbox_flush(osim *s, const jbox *b)
+{
+    size_t q = 0;
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < b->ext[0]; ++i)
+            for (int j = 0; j < b->ext[1]; ++j)
+                for (int k = 0; k < b->ext[2]; ++k, ++q)
+                    if (b->v[q] != 0.0) add_at(s, &s->Jb[c], b->lo[0] + i, b->lo[1] + j, b->lo[2] + k, b->v[q]);
+}
+
+/*
  * Charge-conserving deposit of one macro-particle moving X0 -> X1 (cell
  * units), Esirkepov, Comput. Phys. Commun. 135 (2001) 144, first-order
  * shape S(t) = max(0, 1-|t|) at the nodes.  Over a 4-node window per axis
  * starting one node below the start cell:
  *   Wx = dSx (S0y S0z + dSy S0z/2 + S0y dSz/2 + dSy dSz/3)   (and cyclic),
  *   Jx(i+1/2) = -(q w / (dt dx^2)) sum_{i' <= i} Wx(i')      (and cyclic).
+ * The window must lie inside the box.
  */
-static void deposit(osim *s, const double *X0, const double *X1, double qw)
+static void deposit(osim *s, jbox *box, const double *X0, const double *X1, double qw)
 {
     int base[3];
     double S0[3][4], S1[3][4], dS[3][4];
@@ -668,7 +701,7 @@ static void deposit(osim *s, const double *X0, const double *X1, double qw)
             for (int m = 0; m < 3; ++m) {
                 acc += dS[0][m] * (S0[1][b] * S0[2][c] + 0.5 * dS[1][b] * S0[2][c] +
                                    0.5 * S0[1][b] * dS[2][c] + dS[1][b] * dS[2][c] / 3.0);
-                add_at(s, &s->Jb[0], base[0] + m, base[1] + b, base[2] + c, f * acc);
+                jbox_add(box, 0, base[0] + m, base[1] + b, base[2] + c, f * acc);
             }
         }
     for (int a = 0; a < 4; ++a)
@@ -677,7 +710,7 @@ static void deposit(osim *s, const double *X0, const double *X1, double qw)
             for (int m = 0; m < 3; ++m) {
                 acc += dS[1][m] * (S0[0][a] * S0[2][c] + 0.5 * dS[0][a] * S0[2][c] +
                                    0.5 * S0[0][a] * dS[2][c] + dS[0][a] * dS[2][c] / 3.0);
-                add_at(s, &s->Jb[1], base[0] + a, base[1] + m, base[2] + c, f * acc);
+                jbox_add(box, 1, base[0] + a, base[1] + m, base[2] + c, f * acc);
             }
         }
     for (int a = 0; a < 4; ++a)
@@ -686,7 +719,7 @@ static void deposit(osim *s, const double *X0, const double *X1, double qw)
             for (int m = 0; m < 3; ++m) {
                 acc += dS[2][m] * (S0[0][a] * S0[1][b] + 0.5 * dS[0][a] * S0[1][b] +
                                    0.5 * S0[0][a] * dS[1][b] + dS[0][a] * dS[1][b] / 3.0);
-                add_at(s, &s->Jb[2], base[0] + a, base[1] + b, base[2] + m, f * acc);
+                jbox_add(box, 2, base[0] + a, base[1] + b, base[2] + m, f * acc);
             }
         }
 }
@@ -695,56 +728,117 @@ static void deposit(osim *s, const double *X0, const double *X1, double qw)
 void osim_deposit_move(osim *s, const double *p0, const double *p1)
 {
     double X0[3], X1[3];
+    jbox box;
     for (int a = 0; a < 3; ++a) {
         X0[a] = p0[a] / s->dx;
         X1[a] = p1[a] / s->dx;
+        box.lo[a] = (int)floor(X0[a]) - 1;
+        box.ext[a] = 4;
     }
-    deposit(s, X0, X1, s->q * s->w);
+    box.v = calloc(3 * 64, sizeof(double));
+    deposit(s, &box, X0, X1, s->q * s->w);
+    jbox_flush(s, &box);
+    free(box.v);
 }
+
+/* Gather, Boris, move and deposit of live particle p; 1 if its move was
+ * deposited, 0 if it left the box. */
+static int push_one(osim *s, jbox *box, long p)
+{
+    const double dx = s->dx;
+    double pos[3] = {s->x[p], s->y[p], s->z[p]};
+    double E[3], B[3], u[3] = {s->ux[p], s->uy[p], s->uz[p]};
+    osim_gather(s, pos, E, B);
+    oracle_boris(s->q, s->m, s->dt, E, B, u);
+    double g = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / (OR_C * OR_C));
+    double X0[3], X1[3];
+    int out = 0;
+    for (int a = 0; a < 3; ++a) {
+        X0[a] = pos[a] / dx;
+        X1[a] = (pos[a] + s->dt * u[a] / g) / dx;
+        if (s->bc[a] != OR_PERIODIC && (X1[a] < 0.0 || X1[a] >= (double)s->n[a])) out = 1;
+    }
+    s->ux[p] = u[0];
+    s->uy[p] = u[1];
+    s->uz[p] = u[2];
+    if (out) {
+        s->alive[p] = 0;
+        return 0;
+    }
+    deposit(s, box, X0, X1, s->q * s->w);
+    for (int a = 0; a < 3; ++a) {
+        if (s->bc[a] == OR_PERIODIC) {
+            double L = (double)s->n[a];
+            X1[a] = fmod(X1[a], L);
+            if (X1[a] < 0.0) X1[a] += L;
+        }
+    }
+    s->x[p] = X1[0] * dx;
+    s->y[p] = X1[1] * dx;
+    s->z[p] = X1[2] * dx;
+    return 1;
+}
+
+/* Particles per chunk of the push; below this count one chunk does all. */
+#define OR_CHUNK_MIN 4096
+#define OR_NCHUNK 16
 
 /*
  * Step 2: gather, push, move, deposit.  A particle whose new position leaves
  * [0, n dx) on a non-periodic axis is deactivated and its last move is not
  * deposited; on a periodic axis it is folded back after the deposit.
+ *
+ * The particles are split by index into a fixed number of chunks (one below
+ * OR_CHUNK_MIN particles), which may run on different threads.  Each chunk
+ * deposits into its own copy of J_b over the box of every deposit window of
+ * this step, and the copies are added to J_b in chunk order, so the result
+ * does not depend on the number of threads.
  */
 static void push_particles(osim *s)
 {
-    const double dx = s->dx;
+    jbox all;
+    long nlive = 0;
+    for (int a = 0; a < 3; ++a) {
+        all.lo[a] = s->n[a];
+        all.ext[a] = 0;
+    }
+    int hi[3] = {-1, -1, -1};
     for (long p = 0; p < s->np; ++p) {
         if (!s->alive[p]) continue;
-        double pos[3] = {s->x[p], s->y[p], s->z[p]};
-        double E[3], B[3], u[3] = {s->ux[p], s->uy[p], s->uz[p]};
-        osim_gather(s, pos, E, B);
-        oracle_boris(s->q, s->m, s->dt, E, B, u);
-        double g = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / (OR_C * OR_C));
-        double X0[3], X1[3];
-        int out = 0;
+        const double pos[3] = {s->x[p], s->y[p], s->z[p]};
         for (int a = 0; a < 3; ++a) {
-            X0[a] = pos[a] / dx;
-            X1[a] = (pos[a] + s->dt * u[a] / g) / dx;
-            if (s->bc[a] != OR_PERIODIC && (X1[a] < 0.0 || X1[a] >= (double)s->n[a])) out = 1;
+            const int f = (int)floor(pos[a] / s->dx);
+            if (f - 1 < all.lo[a]) all.lo[a] = f - 1;
+            if (f + 2 > hi[a]) hi[a] = f + 2;
         }
-        s->ux[p] = u[0];
-        s->uy[p] = u[1];
-        s->uz[p] = u[2];
-        if (out) {
-            s->alive[p] = 0;
-            continue;
-        }
-        deposit(s, X0, X1, s->q * s->w);
-        s->pushes++;
-        for (int a = 0; a < 3; ++a) {
-            if (s->bc[a] == OR_PERIODIC) {
-                double L = (double)s->n[a];
-                X1[a] = fmod(X1[a], L);
-                if (X1[a] < 0.0) X1[a] += L;
-            }
-        }
-        s->x[p] = X1[0] * dx;
-        s->y[p] = X1[1] * dx;
-        s->z[p] = X1[2] * dx;
+        ++nlive;
     }
+    if (nlive == 0) return;
+    size_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        all.ext[a] = hi[a] - all.lo[a] + 1;
+        cells *= (size_t)all.ext[a];
+    }
+    const int nchunk = s->np >= OR_CHUNK_MIN ? OR_NCHUNK : 1;
+    double *buf = calloc((size_t)nchunk * 3 * cells, sizeof(double));
+    long pushed[OR_NCHUNK] = {0};
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int ch = 0; ch < nchunk; ++ch) {
+        jbox box = all;
+        box.v = buf + (size_t)ch * 3 * cells;
+        const long p0 = s->np * ch / nchunk, p1 = s->np * (ch + 1) / nchunk;
+        for (long p = p0; p < p1; ++p)
+            if (s->alive[p]) pushed[ch] += push_one(s, &box, p);
+    }
+    for (int ch = 0; ch < nchunk; ++ch) {
+        jbox box = all;
+        box.v = buf + (size_t)ch * 3 * cells;
+        jbox_flush(s, &box);
+        s->pushes += pushed[ch];
+    }
+    free(buf);
 }
+
 
 void osim_set_particles(osim *s, long n, const double *x, const double *y, const double *z,
                         const double *ux, const double *uy, const double *uz, double q, double m,
@@ -869,6 +963,7 @@ static void jb_load(osim *s, const double *in)
  */
 void osim_prescribe_jb(osim *s, const double *hist, long n)
 {
+    s->pbox_on = 0;
     free(s->presc);
     s->presc = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)osim_jb_size(s));
     memcpy(s->presc, hist, sizeof(double) * (size_t)n * (size_t)osim_jb_size(s));
@@ -876,14 +971,91 @@ void osim_prescribe_jb(osim *s, const double *hist, long n)
     s->presc0 = s->step;
 }
 
+/* Entries of one box record: the box [lo, lo + ext) of each J_b component. */
+static size_t jbox_count(const int *ext) { return (size_t)3 * ext[0] * ext[1] * ext[2]; }
+
+/* Copy the box of J_b to out (component, then x, y, z with z fastest), or
+ * back; box entries beyond a component's own extents hold 0. */
+static void jb_box_copy(osim *s, const int *lo, const int *ext, double *buf, int to_grid)
+{
+    size_t q = 0;
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < ext[0]; ++i)
+            for (int j = 0; j < ext[1]; ++j)
+                for (int k = 0; k < ext[2]; ++k, ++q) {
+                    const int id[3] = {lo[0] + i, lo[1] + j, lo[2] + k};
+                    if (id[0] >= s->Jb[c].n[0] || id[1] >= s->Jb[c].n[1] || id[2] >= s->Jb[c].n[2]) {
+                        if (!to_grid) buf[q] = 0.0;
+                        continue;
+                    }
+                    double *v = &AT(s->Jb[c], id[0], id[1], id[2]);
+                    if (to_grid) *v = buf[q];
+                    else buf[q] = *v;
+                }
+}
+
 /* Step 2 of the step: particles, or the prescribed bunch current. */
 static void source_step(osim *s)
 {
     if (s->presc) {
         long r = s->step - s->presc0;
-        if (r >= 0 && r < s->presc_n) jb_load(s, s->presc + (size_t)r * (size_t)osim_jb_size(s));
+        if (r >= 0 && r < s->presc_n) {
+            if (s->pbox_on)
+                jb_box_copy(s, s->pbox_lo, s->pbox_ext, s->presc + (size_t)r * jbox_count(s->pbox_ext), 1);
+            else
+                jb_load(s, s->presc + (size_t)r * (size_t)osim_jb_size(s));
+        }
     } else {
         push_particles(s);
+    }
+}
+
+/*
+ * Run n steps from the current state and record J_b^{n+1/2} of each step on
+ * the box [lo, lo + ext) of lattice indices (0 <= lo, lo + ext <= n + 1 per
+ * axis; clipped to each component's extents): out[n][3][ext0][ext1][ext2].  Returns the largest |J_b| met outside the
+ * box during the run (0 when the box holds every deposit).
+ */
+double osim_run_record_jb_box(osim *s, long n, const int *lo, const int *ext, double *out)
+{
+    const size_t nb = jbox_count(ext);
+    double outside = 0.0;
+    for (long it = 0; it < n; ++it) {
+        update_H(s);
+        source_step(s);
+        jb_box_copy(s, lo, ext, out + (size_t)it * nb, 0);
+        for (int c = 0; c < 3; ++c) {
+            const ofield *f = &s->Jb[c];
+            for (int i = 0; i < f->n[0]; ++i)
+                for (int j = 0; j < f->n[1]; ++j)
+                    for (int k = 0; k < f->n[2]; ++k) {
+                        const int in = i >= lo[0] && i < lo[0] + ext[0] && j >= lo[1] && j < lo[1] + ext[1] &&
+                                       k >= lo[2] && k < lo[2] + ext[2];
+                        const double v = fabs(AT(*f, i, j, k));
+                        if (!in && v > outside) outside = v;
+                    }
+        }
+        update_E(s);
+        s->step++;
+        sample_probes(s);
+    }
+    return outside;
+}
+
+/* Use the box records of osim_run_record_jb_box as the bunch current of the
+ * next n steps (zero outside the box) instead of pushing particles. */
+void osim_prescribe_jb_box(osim *s, const int *lo, const int *ext, const double *hist, long n)
+{
+    const size_t nb = jbox_count(ext);
+    free(s->presc);
+    s->presc = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * nb);
+    memcpy(s->presc, hist, sizeof(double) * (size_t)n * nb);
+    s->presc_n = n;
+    s->presc0 = s->step;
+    s->pbox_on = 1;
+    for (int a = 0; a < 3; ++a) {
+        s->pbox_lo[a] = lo[a];
+        s->pbox_ext[a] = ext[a];
     }
 }
 

@@ -69,6 +69,11 @@ def _load():
     lib.osim_adj_ptr.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_int)]
     lib.osim_grad.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_double, _dp, _dp, _dp]
+    lib.osim_run_record_jb_box.restype = ctypes.c_double
+    lib.osim_run_record_jb_box.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), _dp]
+    lib.osim_prescribe_jb_box.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int), _dp, ctypes.c_long]
     lib.osim_test_uniform_cpml.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double]
     lib.osim_cpml_profile.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
@@ -250,6 +255,23 @@ class OracleSim:
         hist = _f64(hist)
         assert hist.ndim == 2 and hist.shape[1] == self.jb_size()
         self._lib.osim_prescribe_jb(self._h, _p(hist), hist.shape[0])
+
+    def run_record_jb_box(self, n, lo, ext):
+        """Step n times recording J_b^{n+1/2} on the cell box [lo, lo + ext) of each
+        component: returns (records (n, 3, *ext), largest |J_b| seen outside the box)."""
+        lo_c = (ctypes.c_int * 3)(*[int(v) for v in lo])
+        ext_c = (ctypes.c_int * 3)(*[int(v) for v in ext])
+        out = np.zeros((int(n), 3) + tuple(int(v) for v in ext))
+        outside = self._lib.osim_run_record_jb_box(self._h, int(n), lo_c, ext_c, _p(out))
+        return out, float(outside)
+
+    def prescribe_jb_box(self, lo, ext, hist):
+        """Use hist[r] (3, *ext) on the box as the bunch current of the r-th next step."""
+        hist = _f64(hist)
+        assert hist.shape[1:] == (3,) + tuple(int(v) for v in ext)
+        lo_c = (ctypes.c_int * 3)(*[int(v) for v in lo])
+        ext_c = (ctypes.c_int * 3)(*[int(v) for v in ext])
+        self._lib.osim_prescribe_jb_box(self._h, lo_c, ext_c, _p(hist), hist.shape[0])
 
     def _adj(self, which, c, a=0):
         ext = (ctypes.c_int * 3)()

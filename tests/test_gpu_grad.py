@@ -8,6 +8,8 @@ for fields-only runs, FP32 forward and adjoint against FP64; 1e-3 with a
 bunch, whose FP32 recorded current differs from the oracle's FP64 one by the
 particle tolerance.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -101,6 +103,21 @@ def test_fields_only_gradient_matches_oracle_adjoint(case):
     assert _rel(gw, gwo) <= 1e-5
     assert _rel(gg, ggo) <= 1e-5
     assert np.all(gw[w.wp_map == 0] == 0) and np.all(gg[w.wp_map == 0] == 0)
+
+
+def test_gradient_with_kappa_alpha_layers_matches_oracle_adjoint():
+    """The adjoint's CPML transpose with kappa > 1 and alpha > 0 in every layer."""
+    w = dataclasses.replace(_workload((native.BC_CPML,) * 3, 3, False, seed=11),
+                            pml=(3.0, 1.2, 3.0, 4e6))
+    E = _pulse(w)
+    N, w0 = 150, w.omega[0]
+    Lo, gwo, ggo = _oracle(w, E).grad(N, w0)
+    L, gw, gg = _gpu(w, E).grad(w0, N)
+    print(f"kappa/alpha: L rel {abs(L - Lo) / Lo:.2e}  dwp rel {_rel(gw, gwo):.2e}  "
+          f"dgamma rel {_rel(gg, ggo):.2e}", flush=True)
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert _rel(gw, gwo) <= 1e-5
+    assert _rel(gg, ggo) <= 1e-5
 
 
 @pytest.mark.parametrize("ckpt_every", [0, 7])

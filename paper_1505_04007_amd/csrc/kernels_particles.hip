@@ -353,6 +353,162 @@ __device__ __forceinline__ float wave_reduce64(const float *val, bool mine, int 
 // wavefront together (54 atomic instructions however many lanes).
 constexpr int ROUND_LANES = 3;
 
+// ---- row-union deposit ----
+// A wavefront whose windows share their y and z base and differ only in x
+// (consecutive sorted particles in one grid row, the usual case away from the
+// bunch core) spans a union of windows along x.  Inclusive prefix sums of the
+// 54 slot currents are taken over the wavefront's lanes (six DPP adds per
+// slot), so a run of lanes with the same window sums to P(its last lane) -
+// P(the last lane of the run before it).  When every window has one run (the
+// lanes are sorted), the last lane of each run stores its P as the block of
+// its window in tile `plus` and as the block of the next run's window in tile
+// `minus`: plain LDS stores of whole blocks, no LDS atomics (which issue
+// slowly even when their addresses differ).  Each entry of the union then
+// sums, over the up to three windows covering it, plus - minus of the slot it
+// is in those windows, and goes to J_b in a few coalesced atomic
+// instructions, however many windows the wavefront has.  Lanes that do not
+// deposit carry zeros and a key of -1: their runs store nothing in `plus` and
+// pass the running sum on to `minus`.
+constexpr int UNION_KEYS = 14;           // window bases a union may span
+constexpr int UNION_XW = UNION_KEYS + 2;  // x nodes of the widest union
+// floats per window: 54 slots, 16-byte aligned, and an odd number of 16-byte
+// groups so the readback's lanes (one window apart) fall in different banks
+constexpr int UNION_BLOCK = 60;
+// two zero blocks on each side: the readback's window index t - a runs over
+// -2 .. UNION_XW - 1 without a test
+constexpr int UNION_PAD = 2;
+constexpr int UNION_TILE = (UNION_KEYS + 2 * UNION_PAD) * UNION_BLOCK;
+
+// Reductions over the wavefront in the usual GFX9 pattern: prefix within
+// 16-lane rows, then the row broadcasts; the result is valid at lane 63.
+__device__ __forceinline__ int wave_min_dpp(int v)
+{
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ unsigned wave_or_dpp(unsigned v)
+{
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Inclusive prefix sum over the wavefront's lanes: prefix sums within the
+// 16-lane rows (DPP row shifts, each fused into its add), then the row
+// totals carried across rows.  The two cross-row steps add lane 15 of rows 0
+// and 2 to rows 1 and 3, then lane 31 to rows 2 and 3; each is one DPP add
+// that leaves the other rows untouched, written out because the compiler
+// splits a row-masked DPP add into three instructions.  A DPP read of a VGPR
+// that a VALU instruction has just written needs two wait states: the s_nops.
+__device__ __forceinline__ float wave_prefix(float v)
+{
+#define PIC_PREFIX_STEP(ctrl)                                                                                 \
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, true))
+    PIC_PREFIX_STEP(0x111);  // row_shr:1
+    PIC_PREFIX_STEP(0x112);  // row_shr:2
+    PIC_PREFIX_STEP(0x114);  // row_shr:4
+    PIC_PREFIX_STEP(0x118);  // row_shr:8
+#undef PIC_PREFIX_STEP
+    asm("s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(v));
+    return v;
+}
+
+// Store the 54 values as the block of window k (relative to the union's
+// first base) of a tile.
+__device__ __forceinline__ void union_store(float *tile, int k, const float *val)
+{
+    float4 *d = reinterpret_cast<float4 *>(tile + (k + UNION_PAD) * UNION_BLOCK);
+#pragma unroll
+    for (int q = 0; q < 13; ++q) d[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
+    reinterpret_cast<float2 *>(tile + (k + UNION_PAD) * UNION_BLOCK)[26] = make_float2(val[52], val[53]);
+}
+
+// Union entries of one current component: x position t (0 .. UNION_XW - 1
+// from the first base) and R transverse offsets (r = 0 .. R-1, y-major with NZ
+// z offsets per y offset); the window at base t - a holds the entry as slot
+// S0 + a * SA + r.  All LDS reads are issued first (windows outside the union
+// read the zero padding), then the sums, then one atomic add per nonzero sum;
+// the component is a template argument so that J stays a plain pointer.
+template <int S0, int SA, int NA, int R, int NZ>
+__device__ __forceinline__ void union_flush(float *J, const float *plus, const float *minus, int lane, int base,
+                                            int sy, int sz)
+{
+    constexpr int N = R * UNION_XW;
+    constexpr int IT = (N + 63) / 64;
+    float pv[IT][NA], mv[IT][NA];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = min(it * 64 + lane, N - 1);
+        const int t = e % UNION_XW, r = e / UNION_XW;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const int q = (t - a + UNION_PAD) * UNION_BLOCK + S0 + a * SA + r;
+            pv[it][a] = plus[q];
+            mv[it][a] = minus[q];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = it * 64 + lane;
+        const int t = e % UNION_XW, r = e / UNION_XW;
+        float v = 0.f;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) v += pv[it][a] - mv[it][a];
+        if (e < N && v != 0.f) atomicAdd(J + base + t + sy * (r / NZ) + sz * (r % NZ), v);
+    }
+}
+
+// Deposit of a wavefront whose depositing lanes all have window base
+// (bx, by, bz) with the same by, bz, bxmin <= bx < bxmin + UNION_KEYS, the
+// union inside the grid, and one run of lanes per window.  val: the lane's 54
+// slot currents (0 where it does not deposit); key: bx - bxmin, or -1 for a
+// lane that does not deposit; knext: the key of lane + 1 (-1 past lane 63);
+// last: the lane ends its run.
+__device__ __forceinline__ void deposit_union(const PartArgs &a, float *val, int lane, int key, int knext,
+                                              bool last, int bxmin, int by, int bz, float *plus, float *minus)
+{
+    // one wavefront per workgroup: its LDS operations execute in program
+    // order, and the wave barriers keep the compiler from moving the tiles'
+    // accesses of one phase into another
+    constexpr int N4 = UNION_TILE / 4;
+    for (int e = lane; e < N4; e += 64) {
+        reinterpret_cast<float4 *>(plus)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        reinterpret_cast<float4 *>(minus)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int s = 0; s < 54; ++s) val[s] = wave_prefix(val[s]);
+    __builtin_amdgcn_wave_barrier();
+    if (last && key >= 0) union_store(plus, key, val);
+    if (last && knext >= 0) union_store(minus, knext, val);
+    __builtin_amdgcn_wave_barrier();
+    const int base = bxmin + a.nx * (by + a.ny * bz);
+    const int sy = a.nx, sz = a.nx * a.ny;
+    // the current arrays' addresses held in scalar registers through the
+    // flush (otherwise each conditional atomic reloads its pointer from the
+    // argument block and waits for it)
+    float *J0 = a.Jb[0], *J1 = a.Jb[1], *J2 = a.Jb[2];
+    asm volatile("" : "+s"(J0), "+s"(J1), "+s"(J2));
+    // slots: Jx a*9 + b*3 + c (a edge, b, c nodes); Jy 18 + a*6 + m*3 + c;
+    // Jz 36 + a*6 + b*2 + m (a x node, m edge)
+    union_flush<0, 9, 2, 9, 3>(J0, plus, minus, lane, base, sy, sz);
+    union_flush<18, 6, 3, 6, 3>(J1, plus, minus, lane, base, sy, sz);
+    union_flush<36, 6, 3, 6, 2>(J2, plus, minus, lane, base, sy, sz);
+}
+
 template <int MODE, int PX, int FIX>
 __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
 {
@@ -458,7 +614,32 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
     // per-wavefront push counter (one slot per wavefront of the launch)
     if (lane == 0 && live) a.pushes[p >> 6] += (unsigned long long)__popcll(live);
     unsigned long long rem = live;
-    if (MODE != 1) {
+    if (MODE == 0 && !FIX && live) {
+        // one grid row of windows spanning at least two x bases: the row-union tiles
+        __shared__ float4 tplus4[UNION_TILE / 4], tminus4[UNION_TILE / 4];
+        const int leader = __ffsll((long long)live) - 1;
+        const int by0 = __builtin_amdgcn_readlane(base[1], leader);
+        const int bz0 = __builtin_amdgcn_readlane(base[2], leader);
+        if (__ballot(dep && (base[1] != by0 || base[2] != bz0)) == 0ull) {
+            const int bxmin = wave_min_dpp(dep ? base[0] : INT_MAX);
+            const int bxmax = -wave_min_dpp(dep ? -base[0] : INT_MAX);
+            const bool inside = bxmin >= 0 && bxmax + 2 < a.nx && by0 >= 0 && by0 + 2 < a.ny && bz0 >= 0 &&
+                                bz0 + 2 < a.nz;
+            if (inside && bxmax > bxmin && bxmax - bxmin < UNION_KEYS) {
+                const int key = dep ? base[0] - bxmin : -1;
+                const int knext = __builtin_amdgcn_update_dpp(-1, key, 0x130, 0xf, 0xf, false);  // wave_shl:1
+                const bool last = lane == 63 || knext != key;
+                // one run per window: as many runs as windows
+                const unsigned keys = wave_or_dpp(last && key >= 0 ? 1u << key : 0u);
+                if (__popc(keys) == __popcll(__ballot(last && key >= 0))) {
+                    deposit_union(a, val, lane, key, knext, last, bxmin, by0, bz0, (float *)tplus4,
+                                  (float *)tminus4);
+                    rem = 0;
+                }
+            }
+        }
+    }
+    if (MODE != 1 && rem) {
         // lane l < 54 owns slot l of every round's window: its component and
         // offset from the window's base node, computed once
         int lc, li, lj, lk;
@@ -613,12 +794,25 @@ __device__ __forceinline__ int wave_minmax(int v)
     return v;
 }
 
+// Cell key of a particle position (the lost-particle bucket ncell when it is
+// not live).
+__device__ __forceinline__ int cell_key(float x, float y, float z, int nx, int ny, int nz)
+{
+    if (!live_pos(x, y, z, nx, ny, nz)) return nx * ny * nz;
+    return min((int)x, nx - 1) + nx * (min((int)y, ny - 1) + ny * min((int)z, nz - 1));
+}
+
 // Count particles per cell.  Lanes of a wavefront with the same cell (most
 // of them: the particles are nearly sorted from the last sort) reserve their
 // ranks with one atomic and take consecutive ones in lane order, so the
 // scatter writes them to consecutive places.  The groups are found first and
 // their leaders then issue all their atomics at once, so a wavefront spread
 // over many cells waits for one atomic return, not one per cell.
+// Each run of equal keys in the array's order also counts itself in
+// runs[key] and records its start in first[key]: the scatter keeps the order
+// of a key that forms a single run.  The bunch is loaded ordered by x inside
+// each cell and drifts almost uniformly, so that order survives the sorts
+// and the particles of a wavefront stay ordered by their deposit windows.
 __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
 {
     __shared__ int bb[6];
@@ -660,6 +854,14 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
     if (p < a.n) {
         a.key[p] = key;
         a.rank[p] = rank;
+    }
+    // key of particle p - 1: the lane below, or for lane 0 from its position
+    int kprev = __builtin_amdgcn_update_dpp(-1, key, 0x138, 0xf, 0xf, false);  // wave_shr:1
+    if (lane == 0 && p > 0 && p <= a.n)
+        kprev = cell_key(a.P[pc][0][p - 1], a.P[pc][1][p - 1], a.P[pc][2][p - 1], a.nx, a.ny, a.nz);
+    if (p < a.n && (p == 0 || kprev != key)) {
+        atomicAdd(&a.runs[key], 1);
+        a.first[key] = p;
     }
     // box of the live cells: wavefront min / max, then the workgroup's in LDS
     const bool any = __ballot(in) != 0ull;
@@ -818,7 +1020,8 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_scatter(SortArgs a)
     const int p = blockIdx.x * PBLOCK + threadIdx.x;
     if (p >= a.n) return;
     const int pc = a.st->pcur;
-    const int dst = a.counts[a.key[p]] + a.rank[p];
+    const int k = a.key[p];
+    const int dst = a.counts[k] + (a.runs[k] == 1 ? p - a.first[k] : a.rank[p]);
     for (int c = 0; c < 6; ++c) a.P[pc ^ 1][c][dst] = a.P[pc][c][p];
     a.id[pc ^ 1][dst] = a.id[pc][p];
 }
@@ -841,6 +1044,7 @@ void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s)
     const long long ncount = (long long)a.ncell + 1;
     const int nb = (int)(((long long)a.n + PBLOCK - 1) / PBLOCK);
     launch_fill_i32(a.counts, 0, ncount, s);
+    launch_fill_i32(a.runs, 0, ncount, s);
     if (a.n > 0) {
         hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(PBLOCK), 0, s, a);
         hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(BOX_THREADS), 0, s, a, nb);

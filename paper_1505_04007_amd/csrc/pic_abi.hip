@@ -148,6 +148,8 @@ void build_args(pic_ctx *c)
     sa.key = c->key;
     sa.rank = c->rank;
     sa.counts = c->counts;
+    sa.runs = c->runs;
+    sa.first = c->first;
     sa.box = c->box;
     sa.boxpart = c->boxpart;
     sa.st = c->dstate;
@@ -576,19 +578,37 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
             for (int q = 0; q < 6; ++q) TRY(dalloc(c, &c->P[s][q], (size_t)c->np));
             TRY(dalloc(c, &c->pid[s], (size_t)c->np));
         }
+        std::vector<std::vector<float>> cellpos(3, std::vector<float>((size_t)c->np));
+        for (int q = 0; q < 3; ++q)
+            for (int i = 0; i < c->np; ++i) {
+                float v = (float)(src[q][i] / dx);
+                // keep the FP32 cell coordinate inside [0, n) after rounding
+                if (v >= (float)nn[q]) v = std::nextafter((float)nn[q], 0.f);
+                cellpos[q][i] = v;
+            }
+        // load order: by cell, and by x inside a cell.  The device's sorts keep
+        // the order of every cell whose particles stay contiguous, so under a
+        // near-uniform drift the particles of a wavefront stay ordered by their
+        // deposit windows (pic_read_particles returns the original order).
+        std::vector<std::pair<uint64_t, int>> order((size_t)c->np);
+        for (int i = 0; i < c->np; ++i) {
+            const uint64_t cell = (uint64_t)std::min((int)cellpos[0][i], nn[0] - 1) +
+                                  (uint64_t)nn[0] * ((uint64_t)std::min((int)cellpos[1][i], nn[1] - 1) +
+                                                     (uint64_t)nn[1] * (uint64_t)std::min((int)cellpos[2][i], nn[2] - 1));
+            uint32_t xb;
+            std::memcpy(&xb, &cellpos[0][i], 4);  // x >= 0: the bits order like the values
+            order[i] = {(cell << 32) | xb, i};
+        }
+        std::sort(order.begin(), order.end());
+        std::vector<int> ids(c->np);
+        for (int i = 0; i < c->np; ++i) ids[i] = order[i].second;
         for (int q = 0; q < 6; ++q) {
             stage.emplace_back((size_t)c->np);
-            const double sc = q < 3 ? 1.0 / dx : 1.0 / kC;
-            for (int i = 0; i < c->np; ++i) stage.back()[i] = (float)(src[q][i] * sc);
-            if (q < 3) {
-                // keep the FP32 cell coordinate inside [0, n) after rounding
-                for (int i = 0; i < c->np; ++i)
-                    if (stage.back()[i] >= (float)nn[q]) stage.back()[i] = std::nextafter((float)nn[q], 0.f);
-            }
+            const double sc = 1.0 / kC;
+            for (int i = 0; i < c->np; ++i)
+                stage.back()[i] = q < 3 ? cellpos[q][ids[i]] : (float)(src[q][ids[i]] * sc);
             TRY(upload(c->P[0][q], stage.back().data(), (size_t)c->np * 4));
         }
-        std::vector<int> ids(c->np);
-        for (int i = 0; i < c->np; ++i) ids[i] = i;
         HIP_TRY(c, hipMemcpyAsync(c->pid[0], ids.data(), 4 * (size_t)c->np, hipMemcpyHostToDevice, c->stream));
         // one push counter per wavefront of the push launch
         c->n_wave_slots = ((size_t)c->np + 63) / 64;
@@ -597,6 +617,8 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         TRY(dalloc(c, &c->key, (size_t)c->np));
         TRY(dalloc(c, &c->rank, (size_t)c->np));
         TRY(dalloc(c, &c->counts, (size_t)ncell + 1));
+        TRY(dalloc(c, &c->runs, (size_t)ncell + 1));
+        TRY(dalloc(c, &c->first, (size_t)ncell + 1));
         TRY(dalloc(c, &c->box, 6));
         TRY(dalloc(c, &c->boxpart, 6 * (((size_t)c->np + pic::PBLOCK - 1) / pic::PBLOCK)));
         c->scan_len = pic::scan_tmp_size(ncell + 1);
@@ -700,7 +722,7 @@ pic_status pic_query_sizes(const pic_grid *grid, int64_t nparticles, const pic_o
         total += 2 * 6 * bytes(np, 4) + 2 * bytes(np, 4);    // particle state, ids
         total += bytes((np + 63) / 64, 8);                    // push counters
         total += 2 * bytes(np, 4);                            // sort keys, ranks
-        total += bytes(N + 1, 4) + bytes(6, 4);               // cell counts, box
+        total += 3 * bytes(N + 1, 4) + bytes(6, 4);           // cell counts, runs, run starts; box
         total += bytes(6 * ((np + pic::PBLOCK - 1) / pic::PBLOCK), 4);
         total += bytes(pic::scan_tmp_size(N + 1), 4);
         total += 3 * bytes(N, o.deposit_mode == 2 ? 8 : 4);   // J_b (fixed point: 64-bit)

@@ -62,6 +62,7 @@ struct pic_ctx {
     int *pid[2] = {nullptr, nullptr};
     int pcur = 0;
     int *key = nullptr, *rank = nullptr, *counts = nullptr, *box = nullptr, *scan_tmp = nullptr;
+    int *runs = nullptr, *first = nullptr;  // the sort's per-key run counts and run starts
     int *boxpart = nullptr;  // per-workgroup partial boxes of the sort's count kernel
     int scan_len = 0;
     float ah = 0.f, qd = 0.f;

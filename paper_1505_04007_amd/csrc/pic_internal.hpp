@@ -122,6 +122,11 @@ struct SortArgs {
     int *key;
     int *rank;
     int *counts;  // [ncell + 1]
+    // per key: runs of that key in the array's current order, and where the
+    // (last recorded) run starts; a key with one run is contiguous and keeps
+    // its order in the scatter
+    int *runs;    // [ncell + 1]
+    int *first;   // [ncell + 1]
     int *box;     // [6] bounding box of live cells (lo x, y, z, hi x, y, z)
     int *boxpart; // [6 * count workgroups] each count workgroup's box, reduced into box
     DevState *st;

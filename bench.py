@@ -7,9 +7,12 @@ the 512x256x256-cell (33.5M), 1 nm, 12-cell-CPML grating run with a
 1e7-particle 100 keV bunch; all inputs are resident in HBM before timing.
 
 Prints one JSON line: whole-step Gcell-updates/s as `value`, particle
-pushes/s, the HBM roofline of the dominant kernel (algorithmic bytes per
-launch / HIP-event launch time), and the FP64 oracle timed on host cores on a
-bounded sample of the same workload.
+pushes/s, the roofline of the dominant kernel (its VALU instruction issue rate
+against the chip's issue peak when committed counters exist for its current
+source, with its HBM fraction on algorithmic bytes beside it), the FP64
+oracle timed on the host's cores on the whole workload, and the rest of the
+metric: the 256x128x128 production run's rates, the 16-instance batched sweep
+against its 16 plain runs, and pic_grad against the plain forward run.
 """
 import argparse
 import hashlib
@@ -26,6 +29,9 @@ sys.path.insert(0, ROOT)
 METRIC = ("Gcell-updates/s + particle-pushes/s (FP32) and % HBM roofline; "
           "batched/adjoint vs plain")
 HBM_PEAK_GBS = 8000.0
+# wave64 VALU instructions the chip can issue: 256 CUs x 4 SIMDs, one wave64
+# instruction per SIMD every 4 cycles (16 lanes a cycle) at 2.4 GHz
+VALU_PEAK_G = 256 * 4 * 2.4 / 4
 FAMILIES = ("h_update", "push_deposit", "e_update", "probe", "sort")
 KERNEL_SOURCES = {"h_update": "kernels_fields.hip", "e_update": "kernels_fields.hip",
                   "push_deposit": "kernels_particles.hip", "sort": "kernels_particles.hip",
@@ -94,45 +100,50 @@ def source_sha(fam):
     return h.hexdigest()[:16]
 
 
-def traffic_for(fam, wname):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when no summary exists or the kernel source changed since it was taken."""
+def counters_for(fam, wname):
+    """The committed rocprofv3 counter record of a kernel on a workload (HBM
+    bytes per launch, VALU instructions per launch), or {} when none exists or
+    the kernel source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         rec = json.load(open(path)).get(wname, {}).get(fam)
     except (ValueError, OSError):
-        return None
+        return {}
     if not rec or rec.get("source_sha") != source_sha(fam):
-        return None
-    return rec.get("bytes_per_launch")
+        return {}
+    return rec
 
 
-def cpu_baseline(w, nsub=200_000, steps=16):
-    """The FP64 oracle on the full grid of the same workload for `steps` steps
-    with a 1/(n/nsub) subsample of the bunch; the per-push time is scaled to
-    the full bunch to give the per-step time of the whole workload."""
-    import numpy as np
+def traffic_for(fam, wname):
+    return counters_for(fam, wname).get("bytes_per_launch")
+
+
+def cpu_baseline(w, steps=6):
+    """The FP64 oracle on the whole workload (full grid, every particle) for
+    `steps` steps after one untimed step, its field loops and its particle
+    chunks spread over the host's threads."""
     from oracle import pic_oracle as po
     b = w.bunch
-    idx = np.arange(0, b.n, max(1, b.n // nsub))[:nsub]
-    sub = b.subset(idx)
     o = po.OracleSim(w.nx, w.ny, w.nz, w.dx, w.dt, bc=w.bc, npml=w.npml, pml=w.pml,
                      wp_map=w.wp_map, gamma_map=w.gamma_map)
-    o.set_particles(sub.x, sub.y, sub.z, sub.ux, sub.uy, sub.uz, sub.q, b.m, b.w)
+    o.set_particles(b.x, b.y, b.z, b.ux, b.uy, b.uz, b.q, b.m, b.w)
     o.set_probes(w.probes, w.omega)
+    o.step(1)  # first touch of the arrays, not timed
+    t0 = o.timing()
     o.step(steps)
-    t = o.timing()
-    field_s = t["field_s"] / steps
-    push_s = t["particle_s"] / max(t["pushes"], 1)
-    step_s = field_s + push_s * b.n
-    return {"value": w.cells / step_s / 1e9, "unit": "Gcell-updates/s", "cores": t["threads"],
-            "kind": "oracle",
-            "sample": (f"full {w.nx}x{w.ny}x{w.nz} grid, {steps} steps, {len(idx)} of {b.n} "
-                       f"particles; field time per step {field_s:.2f} s measured, push time "
-                       f"{push_s * 1e6:.2f} us/push scaled to the full bunch"),
-            "particle_pushes_per_s": 1.0 / push_s}
+    t1 = o.timing()
+    field_s = t1["field_s"] - t0["field_s"]
+    part_s = t1["particle_s"] - t0["particle_s"]
+    pushes = t1["pushes"] - t0["pushes"]
+    return {"value": w.cells * steps / (field_s + part_s) / 1e9, "unit": "Gcell-updates/s",
+            "cores": t1["threads"], "kind": "oracle",
+            "sample": (f"the whole workload: {w.nx}x{w.ny}x{w.nz} grid and all {b.n} particles, "
+                       f"{steps} steps after one untimed step; fields {field_s / steps:.3f} s and "
+                       f"particles {part_s / steps:.3f} s per step, both parallel over "
+                       f"{t1['threads']} threads"),
+            "particle_pushes_per_s": pushes / part_s if part_s > 0 else None}
 
 
 def step_bytes(w):
@@ -142,9 +153,10 @@ def step_bytes(w):
             algorithmic_bytes(w, "e_update", 0, (0, 0, 0, -1, -1, -1)) + 48 * npart)
 
 
-def bench_batched(args):
+def run_batched(steps, warmup, tune_reps):
     """16 film/energy instances of uneven size: 16 sequential plain runs vs one
-    batch (one launch per kernel family per step, captured sort-period graph)."""
+    batch (one launch per kernel family per step, captured sort-period graph).
+    Both sides tuned (tune_reps > 0) or on the default tile."""
     import torch
     import pic_inputs as pi
     from paper_1505_04007_amd import native
@@ -155,31 +167,42 @@ def bench_batched(args):
     plain_s = 0.0
     for w in ws:
         sim = native.from_workload(w)
-        if not args.no_tune:
-            sim.tune(reps=5)
-        sim.step(args.warmup)
+        if tune_reps > 0:
+            sim.tune(reps=tune_reps)
+        sim.step(warmup)
         torch.cuda.synchronize()
         p0 = sim.stats()["pushes"]
         t0 = time.perf_counter()
-        sim.step(args.steps)
+        sim.step(steps)
         torch.cuda.synchronize()
         plain_s += time.perf_counter() - t0
         pushes_total += sim.stats()["pushes"] - p0
         sim.close()
         del sim
-    print(f"[bench] 16 plain runs: {plain_s:.3f} s", file=sys.stderr, flush=True)
     sims = [native.from_workload(w) for w in ws]
     batch = native.Batch(sims, use_graph=True)
-    tune = batch.tune(force=0) if args.no_tune else batch.tune(reps=5)
-    batch.step(args.warmup)
+    tune = batch.tune(reps=tune_reps) if tune_reps > 0 else batch.tune(force=0)
+    batch.step(warmup)
     torch.cuda.synchronize()
     p0 = sum(s.stats()["pushes"] for s in sims)
     t0 = time.perf_counter()
-    batch.step(args.steps)
+    batch.step(steps)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     pushes = sum(s.stats()["pushes"] for s in sims) - p0
-    print(f"[bench] batched: {secs:.3f} s", file=sys.stderr, flush=True)
+    batch.close()
+    for s_ in sims:
+        s_.close()
+    return {"ws": ws, "cells": cells, "steps": steps, "plain_s": plain_s, "batched_s": secs,
+            "plain_pushes": pushes_total, "batched_pushes": pushes, "tile": tune}
+
+
+def bench_batched(args):
+    """The batched sweep as its own bench line."""
+    r = run_batched(args.steps, args.warmup, 0 if args.no_tune else 5)
+    ws, cells, secs, plain_s = r["ws"], r["cells"], r["batched_s"], r["plain_s"]
+    tune, pushes, pushes_total = r["tile"], r["batched_pushes"], r["plain_pushes"]
+    print(f"[bench] 16 plain runs: {plain_s:.3f} s, batched: {secs:.3f} s", file=sys.stderr, flush=True)
     gcells = cells * args.steps / secs / 1e9
     plain_g = cells * args.steps / plain_s / 1e9
     sb = sum(step_bytes(w) for w in ws)
@@ -202,7 +225,7 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_adjoint(args):
+def run_adjoint(N, warmup):
     """pic_grad on the 128x64x64, 20 nm film, 1e5-particle workload: the
     differentiated run (a forward run that keeps what the reverse pass needs:
     every step's metal-box state when that fits in half the free device
@@ -213,10 +236,10 @@ def bench_adjoint(args):
     from paper_1505_04007_amd import native
 
     w = pi.film_adjoint()
-    N = args.steps if args.steps is not None else w.steps
+    N = w.steps if N is None else N
     w0 = w.meta["omega0"]
     warm = native.from_workload(w)
-    warm.grad(w0, max(args.warmup, 1))
+    warm.grad(w0, max(warmup, 1))
     warm.close()
     plain = native.from_workload(w)
     torch.cuda.synchronize()
@@ -226,7 +249,6 @@ def bench_adjoint(args):
     tf = time.perf_counter() - t0
     pushes = plain.stats()["pushes"]
     plain.close()
-    print(f"[bench] plain {N} steps: {tf:.3f} s", file=sys.stderr, flush=True)
     sim = native.from_workload(w)
     # pic_grad's automatic choice: every step's metal-box snapshot kept from the
     # forward run when they fit in half the free memory, else sqrt(N) checkpoints
@@ -238,7 +260,17 @@ def bench_adjoint(args):
     L, gw, gg = sim.grad(w0, N)
     torch.cuda.synchronize()
     tg = time.perf_counter() - t0
-    print(f"[bench] pic_grad {N} steps: {tg:.3f} s, L = {L:.4e}", file=sys.stderr, flush=True)
+    sim.close()
+    return {"w": w, "N": N, "plain_s": tf, "grad_s": tg, "pushes": pushes, "L": L, "gw": gw, "gg": gg,
+            "replay": replay}
+
+
+def bench_adjoint(args):
+    """The adjoint workload as its own bench line."""
+    r = run_adjoint(args.steps, args.warmup)
+    w, N, tf, tg, pushes, L, gw, gg, replay = (r["w"], r["N"], r["plain_s"], r["grad_s"], r["pushes"],
+                                               r["L"], r["gw"], r["gg"], r["replay"])
+    print(f"[bench] plain {N} steps: {tf:.3f} s; pic_grad {tg:.3f} s, L = {L:.4e}", file=sys.stderr, flush=True)
     gcells = w.cells * N / tg / 1e9
     out = {"metric": METRIC, "value": round(gcells, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
            "steps": N, "warmup": args.warmup, "ms_per_step": round(1e3 * tg / N, 4),
@@ -257,6 +289,34 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def run_production(steps, warmup):
+    """The 256x128x128, 2 nm, 8-cell-CPML production run (30 nm film, 1e6
+    particles at 50 keV): whole-step Gcell-updates/s and pushes/s, every
+    particle live over the timed steps.  Its state (~0.15 GB) fits in the
+    256 MB Infinity Cache, so its rates are not an HBM measurement."""
+    import torch
+    import pic_inputs as pi
+    from paper_1505_04007_amd import native
+
+    w = pi.film_production()
+    sim = native.from_workload(w)
+    tune = sim.tune(reps=5)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    p0 = sim.stats()["pushes"]
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    return {"workload": w.name, "cells": w.cells, "particles": w.bunch.n, "steps": steps,
+            "value": round(w.cells * steps / secs / 1e9, 3), "unit": "Gcell-updates/s",
+            "particle_pushes_per_s": round((st["pushes"] - p0) / secs, 1),
+            "live_particles": st["live"], "ms_per_step": round(1e3 * secs / steps, 4),
+            "field_tile": [tune["fx"], tune["fy"], tune["order"]]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +325,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="grating40nm_512x256x256_cpml12")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the production, batched and adjoint legs of the default line")
     ap.add_argument("--deposit-mode", type=int, default=0)
     ap.add_argument("--sort-every", type=int, default=None,
                     help="override the workload's cell-sort interval")
@@ -342,10 +404,19 @@ def main():
     roof = None
     if algo is not None:
         ach = algo / avg_s / 1e9
-        tr = traffic_for(dom, w.name)
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
-                "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(avg_s * 1e3, 4)}
+        rec = counters_for(dom, w.name)
+        hbm = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": rec.get("bytes_per_launch")}
+        roof = dict(hbm, kernel=dom, algorithmic_bytes_per_launch=algo, avg_launch_ms=round(avg_s * 1e3, 4))
+        if rec.get("valu_per_launch"):
+            # VALU-issue bound: committed SQ_INSTS_VALU per launch over the live launch time
+            va = rec["valu_per_launch"] / avg_s / 1e9
+            roof = {"bound": "alu", "achieved": round(va, 1), "peak": VALU_PEAK_G,
+                    "unit": "G wave64-VALU-instructions/s", "frac": round(va / VALU_PEAK_G, 4),
+                    "traffic": rec.get("bytes_per_launch"), "kernel": dom,
+                    "valu_per_launch": rec["valu_per_launch"], "avg_launch_ms": round(avg_s * 1e3, 4),
+                    "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac")},
+                    "algorithmic_bytes_per_launch": algo}
     kernels = {}
     for f in FAMILIES:
         ms, n = fams[f]
@@ -356,6 +427,35 @@ def main():
                       "share": round(ms / max(sum(v[0] for v in fams.values()), 1e-12), 3)}
         if b is not None:
             kernels[f]["algo_GBps"] = round(b / (ms / n / 1e3) / 1e9, 1)
+
+    del sim
+    extra = {}
+    if not args.no_extras and args.workload == "grating40nm_512x256x256_cpml12":
+        # the rest of the metric, each on its own workload
+        prod = run_production(100, 20)
+        print(f"[bench] production {prod['workload']}: {prod['value']} Gcell/s, "
+              f"{prod['particle_pushes_per_s']:.3e} pushes/s", file=sys.stderr, flush=True)
+        bt = run_batched(100, 20, 5)
+        cells_b = bt["cells"]
+        plain_g = cells_b * bt["steps"] / bt["plain_s"] / 1e9
+        batch_g = cells_b * bt["steps"] / bt["batched_s"] / 1e9
+        print(f"[bench] batched16: {batch_g:.2f} vs plain {plain_g:.2f} Gcell/s", file=sys.stderr, flush=True)
+        ad = run_adjoint(None, 5)
+        print(f"[bench] adjoint: pic_grad {ad['grad_s']:.3f} s vs plain {ad['plain_s']:.3f} s",
+              file=sys.stderr, flush=True)
+        extra = {
+            "production": prod,
+            "batched_vs_plain": round(batch_g / plain_g, 3),
+            "batched": {"workload": "batched16_film5-80nm_128x64x64-192x96x96", "instances": len(bt["ws"]),
+                        "cells": cells_b, "steps": bt["steps"], "value": round(batch_g, 3),
+                        "plain_sequential_value": round(plain_g, 3), "unit": "Gcell-updates/s",
+                        "particle_pushes_per_s": round(bt["batched_pushes"] / bt["batched_s"], 1),
+                        "field_tile": [bt["tile"]["fx"], bt["tile"]["fy"], bt["tile"]["order"]]},
+            "adjoint_vs_plain": round(ad["grad_s"] / ad["plain_s"], 3),
+            "adjoint": {"workload": ad["w"].name, "steps": ad["N"], "grad_seconds": round(ad["grad_s"], 4),
+                        "plain_forward_seconds": round(ad["plain_s"], 4), "reverse_pass": ad["replay"],
+                        "note": "ratio = time of pic_grad (forward + reverse) / time of the plain forward run"},
+        }
 
     cpu = None
     if not args.no_cpu_baseline and w.bunch is not None:
@@ -372,6 +472,7 @@ def main():
                       "parallelism": "single-gpu"},
            "particle_pushes_per_s": round(pushes / secs, 1),
            "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 

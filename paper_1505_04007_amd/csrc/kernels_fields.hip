@@ -16,8 +16,8 @@
 // Workgroups are remapped so that the tiles one XCD executes form a
 // contiguous range in (x, y, z): neighbours in y and z then share that XCD's
 // L2.  The batched entry points run the same per-cell code for many
-// simulations in one launch: the remapped tile index is looked up in a
-// prefix table of tiles per simulation.
+// simulations in one launch: the remapped tile index is looked up in a table
+// of (simulation, tile) per work unit.
 #include "pic_internal.hpp"
 
 namespace pic {
@@ -294,34 +294,27 @@ __global__ __launch_bounds__(TXW *TYW) void k_e_update(FieldArgs a)
     e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
 
-// Simulation owning global work unit t: start[q] <= t < start[q + 1].
-__device__ __forceinline__ int owner(const int *start, int n, int t)
-{
-    int q = 0;
-    while (q + 1 < n && start[q + 1] <= t) ++q;
-    return q;
-}
-
+// Work unit t of a batched launch belongs to simulation own[t] >> 24 as its
+// own unit own[t] & 0xffffff (a table the host builds: one load per
+// workgroup, whatever the number of simulations).
 template <int TXW, int TYW, int ZO>
-__global__ __launch_bounds__(TXW *TYW) void k_h_update_batch(const FieldArgs *args, const int *start, int n)
+__global__ __launch_bounds__(TXW *TYW) void k_h_update_batch(const FieldArgs *args, const int *own)
 {
-    const int t = xcd_tile();
-    const int q = owner(start, n, t);
-    const FieldArgs &a = args[q];
+    const int o = own[xcd_tile()];
+    const FieldArgs &a = args[o >> 24];
     int i, j, k;
-    if (!tile_cell<TXW, TYW, ZO>(a, t - start[q], i, j, k)) return;
+    if (!tile_cell<TXW, TYW, ZO>(a, o & 0xffffff, i, j, k)) return;
     const DevState s = *a.st;
     h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
 
 template <int TXW, int TYW, int ZO>
-__global__ __launch_bounds__(TXW *TYW) void k_e_update_batch(const FieldArgs *args, const int *start, int n)
+__global__ __launch_bounds__(TXW *TYW) void k_e_update_batch(const FieldArgs *args, const int *own)
 {
-    const int t = xcd_tile();
-    const int q = owner(start, n, t);
-    const FieldArgs &a = args[q];
+    const int o = own[xcd_tile()];
+    const FieldArgs &a = args[o >> 24];
     int i, j, k;
-    if (!tile_cell<TXW, TYW, ZO>(a, t - start[q], i, j, k)) return;
+    if (!tile_cell<TXW, TYW, ZO>(a, o & 0xffffff, i, j, k)) return;
     const DevState s = *a.st;
     e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
 }
@@ -360,16 +353,16 @@ struct ELaunch {
 };
 template <int TXW, int TYW, int ZO>
 struct HBatchLaunch {
-    static void launch(int blocks, hipStream_t s, const FieldArgs *args, const int *start, int n)
+    static void launch(int blocks, hipStream_t s, const FieldArgs *args, const int *own)
     {
-        hipLaunchKernelGGL((k_h_update_batch<TXW, TYW, ZO>), dim3(blocks), dim3(TXW, TYW), 0, s, args, start, n);
+        hipLaunchKernelGGL((k_h_update_batch<TXW, TYW, ZO>), dim3(blocks), dim3(TXW, TYW), 0, s, args, own);
     }
 };
 template <int TXW, int TYW, int ZO>
 struct EBatchLaunch {
-    static void launch(int blocks, hipStream_t s, const FieldArgs *args, const int *start, int n)
+    static void launch(int blocks, hipStream_t s, const FieldArgs *args, const int *own)
     {
-        hipLaunchKernelGGL((k_e_update_batch<TXW, TYW, ZO>), dim3(blocks), dim3(TXW, TYW), 0, s, args, start, n);
+        hipLaunchKernelGGL((k_e_update_batch<TXW, TYW, ZO>), dim3(blocks), dim3(TXW, TYW), 0, s, args, own);
     }
 };
 
@@ -383,14 +376,14 @@ void launch_e_update(const FieldArgs &a, hipStream_t s)
     launch_shape<ELaunch>(a.tile, field_tiles(a.nx, a.ny, a.nz, a.tile), s, a);
 }
 
-void launch_h_update_batch(const FieldArgs *args, const int *start, int n, int total, int shape, hipStream_t s)
+void launch_h_update_batch(const FieldArgs *args, const int *own, int total, int shape, hipStream_t s)
 {
-    launch_shape<HBatchLaunch>(shape, total, s, args, start, n);
+    launch_shape<HBatchLaunch>(shape, total, s, args, own);
 }
 
-void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int total, int shape, hipStream_t s)
+void launch_e_update_batch(const FieldArgs *args, const int *own, int total, int shape, hipStream_t s)
 {
-    launch_shape<EBatchLaunch>(shape, total, s, args, start, n);
+    launch_shape<EBatchLaunch>(shape, total, s, args, own);
 }
 
 }  // namespace pic

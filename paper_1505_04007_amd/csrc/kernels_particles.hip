@@ -722,16 +722,13 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit(PartArgs a)
     push_body<MODE, PX, FIX>(a, blockIdx.x);
 }
 
-// Many simulations in one launch: workgroup b belongs to the simulation q
-// with start[q] <= b < start[q + 1].
+// Many simulations in one launch: workgroup b is push block own[b] & 0xffffff
+// of simulation own[b] >> 24 (a table the host builds).
 template <int MODE, int PX>
-__global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit_batch(const PartArgs *args, const int *start,
-                                                               int n)
+__global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit_batch(const PartArgs *args, const int *own)
 {
-    const int b = blockIdx.x;
-    int q = 0;
-    while (q + 1 < n && start[q + 1] <= b) ++q;
-    push_body<MODE, PX, 0>(args[q], b - start[q]);
+    const int o = own[blockIdx.x];
+    push_body<MODE, PX, 0>(args[o >> 24], o & 0xffffff);
 }
 
 void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s)
@@ -752,15 +749,14 @@ void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s)
 }
 
 // `mode` bit 0: per-lane atomics; bit 1: some simulation has a periodic x axis.
-void launch_push_deposit_batch(const PartArgs *args, const int *start, int n, int total, int mode,
-                               hipStream_t s)
+void launch_push_deposit_batch(const PartArgs *args, const int *own, int total, int mode, hipStream_t s)
 {
     if (total <= 0) return;
     switch (mode & 3) {
-    case 0: hipLaunchKernelGGL((k_push_deposit_batch<0, 0>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, start, n); break;
-    case 1: hipLaunchKernelGGL((k_push_deposit_batch<1, 0>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, start, n); break;
-    case 2: hipLaunchKernelGGL((k_push_deposit_batch<0, 1>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, start, n); break;
-    default: hipLaunchKernelGGL((k_push_deposit_batch<1, 1>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, start, n); break;
+    case 0: hipLaunchKernelGGL((k_push_deposit_batch<0, 0>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, own); break;
+    case 1: hipLaunchKernelGGL((k_push_deposit_batch<1, 0>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, own); break;
+    case 2: hipLaunchKernelGGL((k_push_deposit_batch<0, 1>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, own); break;
+    default: hipLaunchKernelGGL((k_push_deposit_batch<1, 1>), dim3(total), dim3(PUSH_BLOCK), 0, s, args, own); break;
     }
 }
 

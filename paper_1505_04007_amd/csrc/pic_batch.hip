@@ -15,7 +15,8 @@ struct pic_batch {
     pic::FieldArgs *d_fa = nullptr;
     pic::PartArgs *d_pa = nullptr;
     pic::ProbeArgs *d_pr = nullptr;
-    int *d_tiles = nullptr, *d_pblocks = nullptr;
+    int *d_tiles = nullptr, *d_pblocks = nullptr;  // per work unit: member << 24 | its own unit
+    size_t tiles_cap = 0;                          // entries d_tiles holds (the largest tile shape's count)
     int total_tiles = 0, total_pblocks = 0;
     int push_mode = 0;  // bit 0: per-lane atomics, bit 1: some member has a periodic x axis
     int sort_every = 0;
@@ -65,10 +66,10 @@ void batch_free(pic_batch *b)
 void batch_launches(pic_batch *b)
 {
     const int n = (int)b->ctx.size();
-    pic::launch_h_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, b->tile, b->stream);
+    pic::launch_h_update_batch(b->d_fa, b->d_tiles, b->total_tiles, b->tile, b->stream);
     if (b->particles)
-        pic::launch_push_deposit_batch(b->d_pa, b->d_pblocks, n, b->total_pblocks, b->push_mode, b->stream);
-    pic::launch_e_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, b->tile, b->stream);
+        pic::launch_push_deposit_batch(b->d_pa, b->d_pblocks, b->total_pblocks, b->push_mode, b->stream);
+    pic::launch_e_update_batch(b->d_fa, b->d_tiles, b->total_tiles, b->tile, b->stream);
     pic::launch_probe_batch(b->d_pr, n, b->stream);
 }
 
@@ -94,25 +95,38 @@ pic_status batch_sorts(pic_batch *b, bool only_due)
     return PIC_OK;
 }
 
+// Work-unit table of a batched launch: counts[q] units of member q, in member
+// order; entry = q << 24 | the unit's index within member q.
+std::vector<int> unit_table(const std::vector<long long> &counts)
+{
+    std::vector<int> t;
+    for (size_t q = 0; q < counts.size(); ++q)
+        for (long long u = 0; u < counts[q]; ++u) t.push_back((int)(q << 24) | (int)u);
+    return t;
+}
+
 // Field argument blocks of every member for tile shape `shape`, and the
-// prefix table of tiles per member.
+// field launches' work-unit table (re-made when the tuner changes the shape).
 pic_status batch_upload_fields(pic_batch *b, int shape)
 {
     const int n = (int)b->ctx.size();
     std::vector<pic::FieldArgs> fa(n);
-    std::vector<int> tiles(n + 1, 0);
+    std::vector<long long> tiles(n);
     for (int q = 0; q < n; ++q) {
         const pic_ctx *c = b->ctx[q];
         fa[q] = c->fa;
         fa[q].tile = shape;
         fa[q].gx = (c->n[0] + pic::TILE_FX[shape] - 1) / pic::TILE_FX[shape];
         fa[q].gy = (c->n[1] + pic::TILE_FY[shape] - 1) / pic::TILE_FY[shape];
-        tiles[q + 1] = tiles[q] + pic::field_tiles(c->n[0], c->n[1], c->n[2], shape);
+        tiles[q] = pic::field_tiles(c->n[0], c->n[1], c->n[2], shape);
+        if (tiles[q] >= (1LL << 24)) return bfail(b, PIC_EINVAL, "member %d has too many field tiles for a batch", q);
     }
+    const std::vector<int> tab = unit_table(tiles);
+    if (tab.size() > b->tiles_cap) return bfail(b, PIC_EINVAL, "field tile table larger than allocated");
     BHIP(b, hipMemcpy(b->d_fa, fa.data(), sizeof(pic::FieldArgs) * n, hipMemcpyHostToDevice));
-    BHIP(b, hipMemcpy(b->d_tiles, tiles.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_tiles, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice));
     b->tile = shape;
-    b->total_tiles = tiles[n];
+    b->total_tiles = (int)tab.size();
     return PIC_OK;
 }
 
@@ -146,7 +160,7 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
 {
     std::vector<pic::PartArgs> pa(n);
     std::vector<pic::ProbeArgs> pr(n);
-    std::vector<int> pblk(n + 1, 0);
+    std::vector<long long> pblk(n, 0);
     for (int q = 0; q < n; ++q) {
         pic_ctx *c = ctxs[q];
         if (!c || c->poisoned) return bfail(b, PIC_EINVAL, "context %d is NULL or poisoned", q);
@@ -167,26 +181,37 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
         b->ctx.push_back(c);
         pa[q] = c->pa;
         pr[q] = c->pr;
-        const long long nb = pblk[q] + ((long long)c->np + pic::PUSH_BLOCK - 1) / pic::PUSH_BLOCK;
-        if (nb > INT_MAX) return bfail(b, PIC_EINVAL, "too many particles in the batch for one launch");
-        pblk[q + 1] = (int)nb;
+        pblk[q] = ((long long)c->np + pic::PUSH_BLOCK - 1) / pic::PUSH_BLOCK;
     }
+    long long total_pb = 0;
+    for (long long v : pblk) total_pb += v;
+    if (total_pb > INT_MAX) return bfail(b, PIC_EINVAL, "too many particles in the batch for one launch");
+    const std::vector<int> ptab = unit_table(pblk);
     b->ext = ctxs[0]->stream;
     // an own stream: the members' stream may be the null stream, which cannot be captured
     BHIP(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     BHIP(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     BHIP(b, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
-    b->total_pblocks = pblk[n];
+    b->total_pblocks = (int)ptab.size();
     BHIP(b, hipMalloc(&b->d_fa, sizeof(pic::FieldArgs) * n));
     BHIP(b, hipMalloc(&b->d_pa, sizeof(pic::PartArgs) * n));
     BHIP(b, hipMalloc(&b->d_pr, sizeof(pic::ProbeArgs) * n));
-    BHIP(b, hipMalloc(&b->d_tiles, sizeof(int) * (n + 1)));
-    BHIP(b, hipMalloc(&b->d_pblocks, sizeof(int) * (n + 1)));
+    BHIP(b, hipMalloc(&b->d_pblocks, sizeof(int) * std::max<size_t>(ptab.size(), 1)));
+    // the field tile table for the shape with the most tiles, so the tuner
+    // rewrites it in place
+    for (int v = 0; v < pic::N_TILE_SHAPES; ++v) {
+        long long t = 0;
+        for (pic_ctx *c : b->ctx) t += pic::field_tiles(c->n[0], c->n[1], c->n[2], v);
+        if (t > INT_MAX) return bfail(b, PIC_EINVAL, "too many field tiles in the batch for one launch");
+        b->tiles_cap = std::max(b->tiles_cap, (size_t)t);
+    }
+    BHIP(b, hipMalloc(&b->d_tiles, sizeof(int) * std::max<size_t>(b->tiles_cap, 1)));
     pic_status st = batch_upload_fields(b, 0);
     if (st != PIC_OK) return st;
     BHIP(b, hipMemcpy(b->d_pa, pa.data(), sizeof(pic::PartArgs) * n, hipMemcpyHostToDevice));
     BHIP(b, hipMemcpy(b->d_pr, pr.data(), sizeof(pic::ProbeArgs) * n, hipMemcpyHostToDevice));
-    BHIP(b, hipMemcpy(b->d_pblocks, pblk.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    if (!ptab.empty())
+        BHIP(b, hipMemcpy(b->d_pblocks, ptab.data(), sizeof(int) * ptab.size(), hipMemcpyHostToDevice));
     b->use_graph = use_graph != 0;
     if (b->use_graph) return batch_capture(b);
     return PIC_OK;
@@ -279,16 +304,15 @@ pic_status pic_batch_tune(pic_batch *b, int32_t reps, int32_t force, pic_tune_ou
         if (st == PIC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
             st = bfail(b, PIC_EDEVICE, "hipEventCreate failed");
         if (st == PIC_OK && hipStreamSynchronize(b->ext) != hipSuccess) st = bfail(b, PIC_EDEVICE, "sync failed");
-        const int n = (int)b->ctx.size();
         for (int v = 0; v < pic::N_TILE_SHAPES && st == PIC_OK; ++v) {
             st = batch_upload_fields(b, v);
             if (st != PIC_OK) break;
-            pic::launch_h_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, v, b->stream);
-            pic::launch_e_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, v, b->stream);
+            pic::launch_h_update_batch(b->d_fa, b->d_tiles, b->total_tiles, v, b->stream);
+            pic::launch_e_update_batch(b->d_fa, b->d_tiles, b->total_tiles, v, b->stream);
             (void)hipEventRecord(e0, b->stream);
             for (int r = 0; r < reps; ++r) {
-                pic::launch_h_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, v, b->stream);
-                pic::launch_e_update_batch(b->d_fa, b->d_tiles, n, b->total_tiles, v, b->stream);
+                pic::launch_h_update_batch(b->d_fa, b->d_tiles, b->total_tiles, v, b->stream);
+                pic::launch_e_update_batch(b->d_fa, b->d_tiles, b->total_tiles, v, b->stream);
             }
             (void)hipEventRecord(e1, b->stream);
             float t = 0.f;

@@ -204,12 +204,12 @@ void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s);
 int scan_tmp_size(long long n);
 
 // Batched forms: one launch over many simulations.  `args` is a device array
-// of per-simulation argument blocks; `start` a device prefix table of work
-// units (field tiles / particle workgroups) per simulation, start[n] = total.
-void launch_h_update_batch(const FieldArgs *args, const int *start, int n, int total, int shape, hipStream_t s);
-void launch_e_update_batch(const FieldArgs *args, const int *start, int n, int total, int shape, hipStream_t s);
-void launch_push_deposit_batch(const PartArgs *args, const int *start, int n, int total, int mode,
-                               hipStream_t s);
+// of per-simulation argument blocks; `own` a device table with one entry per
+// work unit of the launch (field tile / particle workgroup, `total` of them):
+// simulation index << 24 | the unit's index within that simulation.
+void launch_h_update_batch(const FieldArgs *args, const int *own, int total, int shape, hipStream_t s);
+void launch_e_update_batch(const FieldArgs *args, const int *own, int total, int shape, hipStream_t s);
+void launch_push_deposit_batch(const PartArgs *args, const int *own, int total, int mode, hipStream_t s);
 void launch_probe_batch(const ProbeArgs *args, int n, hipStream_t s);
 
 // ---- reverse-time adjoint of the linear field step (bunch current fixed) ----

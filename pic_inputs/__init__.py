@@ -276,7 +276,7 @@ PAPER_GAMMA = 1.45e13
 
 def paper_film(d_nm, dx=2e-9, t_fs=40.0, gap_nm=10.0, kinetic_ev=100e3, nparticles=4000,
                npml=10, current_density=1e9, below_nm=100.0, above_nm=100.0, probe_um=1.5,
-               gamma=PAPER_GAMMA):
+               gamma=PAPER_GAMMA, past_probe_nm=None, ny=4, pml_alpha=0.0, f_thz=(500.0, 1800.0, 1.0)):
     """The paper's geometry (Sec. III): film normal along x, bunch along +z,
     periodic y, Ez probe on the film surface 1.5 um downstream of the bunch start.
 
@@ -290,20 +290,32 @@ def paper_film(d_nm, dx=2e-9, t_fs=40.0, gap_nm=10.0, kinetic_ev=100e3, nparticl
     truncated, cold, along +z, with the peak current density of Sec. III
     (100 kA/cm^2 = 1e9 A/m^2): Q = J ly 2 pi sx sz / v.  At that density the
     bunch's space charge is negligible and it moves on straight lines.
+    probe_um: one distance or several (one probe each, same run); the first
+    is the paper's.  past_probe_nm: end the domain this far past the last probe
+    instead (the bunch then leaves through the far absorbing layer and the
+    probes record the surface modes ringing down; long records stay
+    affordable).  ny: periodic cells across the beam (the sheet bunch drives
+    no y wavenumber, so one cell is the same problem).  pml_alpha: CFS shift
+    alpha_max of the layers (S/m).  f_thz: (first, last, step) of the probe
+    DFT grid in THz.
     """
     rng = np.random.default_rng(SEED0 + 5)
     i0 = npml + int(round(below_nm * 1e-9 / dx))
     i1 = i0 + int(round(d_nm * 1e-9 / dx))
     nx = i1 + int(round(above_nm * 1e-9 / dx)) + npml
-    ny = 4
     dt = courant_dt(dx)
+    pz = np.atleast_1d(np.asarray(probe_um, dtype=np.float64))
     g = 1.0 + kinetic_ev / MEC2_EV
     v = C_LIGHT * np.sqrt(1.0 - 1.0 / (g * g))
     steps = int(np.ceil(t_fs * 1e-15 / dt))
     z0 = (npml + 12) * dx + 15e-9
-    zp = z0 + probe_um * 1e-6
-    z_end = z0 + v * steps * dt + 80e-9
-    nz = int(np.ceil(max(z_end, zp + 200e-9) / dx)) + npml
+    zps = z0 + pz * 1e-6
+    zp = zps[0]
+    if past_probe_nm is None:
+        z_end = max(z0 + v * steps * dt + 80e-9, zps.max() + 200e-9)
+    else:
+        z_end = zps.max() + past_probe_nm * 1e-9
+    nz = int(np.ceil(z_end / dx)) + npml
     wpm = np.zeros((nx, ny, nz))
     gm = np.zeros((nx, ny, nz))
     wpm[i0:i1] = PAPER_WP
@@ -316,13 +328,13 @@ def paper_film(d_nm, dx=2e-9, t_fs=40.0, gap_nm=10.0, kinetic_ev=100e3, nparticl
     charge = current_density * ny * dx * 2 * np.pi * 2e-9 * 5e-9 / v
     bunch = Bunch(xs, ys, zs, np.zeros(nparticles), np.zeros(nparticles), np.full(nparticles, u),
                   -E_CHARGE, M_E, charge / (nparticles * E_CHARGE))
-    probes = np.array([[top + 1e-9, ny * dx / 2, zp]])
-    omega = 2 * np.pi * 1e12 * np.arange(500.0, 1800.0, 1.0)  # 1 THz grid
+    probes = np.array([[top + 1e-9, (ny // 2) * dx, z] for z in zps])
+    omega = 2 * np.pi * 1e12 * np.arange(*f_thz)
     return Workload(f"paperfilm{d_nm}nm_{nx}x{ny}x{nz}", nx, ny, nz, dx, dt, (CPML, PERIODIC, CPML),
                     npml, wpm, gm, bunch, probes, omega, steps,
-                    sort_every=20,
-                    meta={"thickness_nm": d_nm, "z0": z0, "z_probe": zp, "v": v, "film_top": top,
-                          "gamma": gamma})
+                    pml=(3.0, 1.0, 1.0, float(pml_alpha)), sort_every=20,
+                    meta={"thickness_nm": d_nm, "z0": z0, "z_probe": zp, "z_probes": zps, "v": v,
+                          "film_top": top, "gamma": gamma})
 
 
 # ---------------------------------------------------------------------------

@@ -11,29 +11,30 @@ namespace pic {
 __device__ __forceinline__ void probe_body(const ProbeArgs &a)
 {
     const int t = threadIdx.x;
-    const long long n1 = a.st->step + 1;  // E^{n+1} was just computed
+    const gp<DevState> st = G(a.st);
+    const gp<const float> Ez = G(a.Ez);
+    const gp<const int> pidx = G(a.pidx);
+    const long long n1 = st->step + 1;  // E^{n+1} was just computed
     const double tn = (double)n1 * a.dt;
     for (int q = t; q < a.nprobe * a.nfreq; q += blockDim.x) {
         const int p = q / a.nfreq, f = q - p * a.nfreq;
-        const double ez = (double)a.Ez[a.pidx[p]];
+        const double ez = (double)Ez[pidx[p]];
         double sn, cs;
-        sincos(a.omega[f] * tn, &sn, &cs);
-        a.fre[q] += a.dt * ez * cs;
-        a.fim[q] -= a.dt * ez * sn;
+        sincos(G(a.omega)[f] * tn, &sn, &cs);
+        G(a.fre)[q] += a.dt * ez * cs;
+        G(a.fim)[q] -= a.dt * ez * sn;
     }
     if (a.series && t < a.nprobe && n1 - 1 < a.series_len)
-        a.series[(n1 - 1) * a.nprobe + t] = a.Ez[a.pidx[t]];
+        G(a.series)[(n1 - 1) * a.nprobe + t] = Ez[pidx[t]];
     if (a.gser && t < a.nprobe && n1 > a.g0 && n1 <= a.g0 + a.gn)
-        a.gser[(n1 - a.g0 - 1) * a.nprobe + t] = (double)a.Ez[a.pidx[t]];
+        G(a.gser)[(n1 - a.g0 - 1) * a.nprobe + t] = (double)Ez[pidx[t]];
     __syncthreads();  // every thread has read the clock before it moves
     if (t == 0) {
-        DevState *st = a.st;
         st->parity ^= 1;
         st->since_sort += 1;
         st->step = n1;
     }
 }
-
 __global__ void k_probe(ProbeArgs a) { probe_body(a); }
 
 __global__ void k_probe_batch(const ProbeArgs *args) { probe_body(args[blockIdx.x]); }

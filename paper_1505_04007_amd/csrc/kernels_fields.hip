@@ -16,8 +16,8 @@
 // Workgroups are remapped so that the tiles one XCD executes form a
 // contiguous range in (x, y, z): neighbours in y and z then share that XCD's
 // L2.  The batched entry points run the same per-cell code for many
-// simulations in one launch: the remapped tile index is looked up in a table
-// of (simulation, tile) per work unit.
+// simulations in one launch: the remapped work-unit index is looked up in a
+// table of (simulation, group of consecutive tiles).
 #include "pic_internal.hpp"
 
 namespace pic {
@@ -30,8 +30,8 @@ __device__ __forceinline__ int lin(const FieldArgs &a, int i, int j, int k)
 // Values a cell reads or writes once, that no neighbour touches in the same
 // launch, are streamed past the caches so they keep the stencil's shared
 // neighbour data.
-__device__ __forceinline__ float ld_once(const float *p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ void st_once(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ float ld_once(const float *p) { return __builtin_nontemporal_load(G(p)); }
+__device__ __forceinline__ void st_once(float *p, float v) { __builtin_nontemporal_store(v, G(p)); }
 
 // One CPML axis of one cell: its slab index, coefficients and two memories,
 // loaded with the cell's field values (all issued before any is used, so a
@@ -48,11 +48,11 @@ __device__ __forceinline__ SlabMem slab_load(float *const *psi, const float *tb,
 {
     SlabMem m{in, sid, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (in) {
-        m.b = tb[pos];
-        m.c = tc[pos];
-        m.ik = tk[pos];
-        m.p0 = psi[0][sid];
-        m.p1 = psi[1][sid];
+        m.b = G(tb)[pos];
+        m.c = G(tc)[pos];
+        m.ik = G(tk)[pos];
+        m.p0 = G(psi[0])[sid];
+        m.p1 = G(psi[1])[sid];
     }
     return m;
 }
@@ -60,7 +60,7 @@ __device__ __forceinline__ SlabMem slab_load(float *const *psi, const float *tb,
 __device__ __forceinline__ float cpml_update(float *__restrict__ psi, const SlabMem &m, float p, float d)
 {
     const float s = m.b * p + m.c * d;
-    psi[m.sid] = s;
+    G(psi)[m.sid] = s;
     return d * m.ik + s;
 }
 
@@ -87,11 +87,12 @@ __device__ __forceinline__ bool in_particle_box(const FieldArgs &a, int margin, 
 {
     const int n3[3] = {a.nx, a.ny, a.nz};
     const int id3[3] = {i, j, k};
+    const gp<const int> box = G(a.pbox);
     bool in = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int lo = a.per[d] ? 0 : a.pbox[d] - margin;
-        const int hi = a.per[d] ? n3[d] - 1 : a.pbox[3 + d] + margin;
+        const int lo = a.per[d] ? 0 : box[d] - margin;
+        const int hi = a.per[d] ? n3[d] - 1 : box[3 + d] + margin;
         in = in && id3[d] >= lo && id3[d] <= hi;
     }
     return in;
@@ -106,9 +107,9 @@ __device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, 
     const int ox = nb_off(i, 1, a.nx, a.per[0], sx, okx);
     const int oy = nb_off(j, 1, a.ny, a.per[1], sy, oky);
     const int oz = nb_off(k, 1, a.nz, a.per[2], sz, okz);
-    const float *__restrict__ Ex = a.E[0];
-    const float *__restrict__ Ey = a.E[1];
-    const float *__restrict__ Ez = a.E[2];
+    const gp<const float> __restrict__ Ex = G(a.E[0]);
+    const gp<const float> __restrict__ Ey = G(a.E[1]);
+    const gp<const float> __restrict__ Ez = G(a.E[2]);
     const float *__restrict__ H0 = par ? a.H[1][0] : a.H[0][0];
     const float *__restrict__ H1 = par ? a.H[1][1] : a.H[0][1];
     const float *__restrict__ H2 = par ? a.H[1][2] : a.H[0][2];
@@ -152,9 +153,9 @@ __device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, 
     st_once(O2 + id, nhz);
     if (a.Havg[0] && in_particle_box(a, margin, i, j, k)) {
         // B^n of the push, (Ht^{n-1/2} + Ht^{n+1/2})/2, where particles can gather it
-        a.Havg[0][id] = 0.5f * (hx + nhx);
-        a.Havg[1][id] = 0.5f * (hy + nhy);
-        a.Havg[2][id] = 0.5f * (hz + nhz);
+        G(a.Havg[0])[id] = 0.5f * (hx + nhx);
+        G(a.Havg[1])[id] = 0.5f * (hy + nhy);
+        G(a.Havg[2])[id] = 0.5f * (hz + nhz);
     }
 }
 
@@ -171,9 +172,9 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
     const int oy = nb_off(j, -1, a.ny, a.per[1], sy, oky);
     const int oz = nb_off(k, -1, a.nz, a.per[2], sz, okz);
     // H^{n+1/2}: written by this step's H update into H[par ^ 1]
-    const float *__restrict__ Hx = par ? a.H[0][0] : a.H[1][0];
-    const float *__restrict__ Hy = par ? a.H[0][1] : a.H[1][1];
-    const float *__restrict__ Hz = par ? a.H[0][2] : a.H[1][2];
+    const gp<const float> __restrict__ Hx = G(par ? a.H[0][0] : a.H[1][0]);
+    const gp<const float> __restrict__ Hy = G(par ? a.H[0][1] : a.H[1][1]);
+    const gp<const float> __restrict__ Hz = G(par ? a.H[0][2] : a.H[1][2]);
     const float hx = Hx[id], hy = Hy[id], hz = Hz[id];
     float hyx = Hy[id + ox], hzx = Hz[id + ox];
     float hxy = Hx[id + oy], hzy = Hz[id + oy];
@@ -210,24 +211,26 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
         k < a.mhi[2]) {
         const int wx = a.mhi[0] - a.mlo[0], wy = a.mhi[1] - a.mlo[1];
         const int bi = (i - a.mlo[0]) + wx * ((j - a.mlo[1]) + wy * (k - a.mlo[2]));
-        const float2 cd = a.coef[bi];
-        float jx = a.Jp[0][bi], jy = a.Jp[1][bi], jz = a.Jp[2][bi];
+        const fvec2 cd = *(gp<const fvec2>)G(a.coef + bi);
+        const gp<float> J0 = G(a.Jp[0]), J1 = G(a.Jp[1]), J2 = G(a.Jp[2]);
+        float jx = J0[bi], jy = J1[bi], jz = J2[bi];
         if (a.snap) {
             // the reverse pass's snapshot: E^n and J_pol^{n-1/2} of this cell
             const int nb = wx * wy * (a.mhi[2] - a.mlo[2]);
-            a.snap[bi] = ex;
-            a.snap[nb + bi] = ey;
-            a.snap[2 * nb + bi] = ez;
-            a.snap[3 * nb + bi] = jx;
-            a.snap[4 * nb + bi] = jy;
-            a.snap[5 * nb + bi] = jz;
+            const gp<float> sn = G(a.snap);
+            sn[bi] = ex;
+            sn[nb + bi] = ey;
+            sn[2 * nb + bi] = ez;
+            sn[3 * nb + bi] = jx;
+            sn[4 * nb + bi] = jy;
+            sn[5 * nb + bi] = jz;
         }
         jx += cd.x * ex - cd.y * jx;
         jy += cd.x * ey - cd.y * jy;
         jz += cd.x * ez - cd.y * jz;
-        a.Jp[0][bi] = jx;
-        a.Jp[1][bi] = jy;
-        a.Jp[2][bi] = jz;
+        J0[bi] = jx;
+        J1[bi] = jy;
+        J2[bi] = jz;
         nex -= jx;
         ney -= jy;
         nez -= jz;
@@ -235,26 +238,29 @@ __device__ __forceinline__ void e_cell(const FieldArgs &a, int par, int margin, 
     if (a.pbox && in_particle_box(a, margin, i, j, k)) {
         if (a.Jq[0]) {
             // fixed-point bunch current (deterministic deposit), FP64 to V/m
-            nex -= (float)((double)(long long)a.Jq[0][id] * a.qinv);
-            ney -= (float)((double)(long long)a.Jq[1][id] * a.qinv);
-            nez -= (float)((double)(long long)a.Jq[2][id] * a.qinv);
-            a.Jq[0][id] = 0ull;
-            a.Jq[1][id] = 0ull;
-            a.Jq[2][id] = 0ull;
+            const gp<unsigned long long> q0 = G(a.Jq[0]), q1 = G(a.Jq[1]), q2 = G(a.Jq[2]);
+            nex -= (float)((double)(long long)q0[id] * a.qinv);
+            ney -= (float)((double)(long long)q1[id] * a.qinv);
+            nez -= (float)((double)(long long)q2[id] * a.qinv);
+            q0[id] = 0ull;
+            q1[id] = 0ull;
+            q2[id] = 0ull;
         } else {
-            nex -= a.Jb[0][id];
-            ney -= a.Jb[1][id];
-            nez -= a.Jb[2][id];
-            a.Jb[0][id] = 0.f;
-            a.Jb[1][id] = 0.f;
-            a.Jb[2][id] = 0.f;
+            const gp<float> b0 = G(a.Jb[0]), b1 = G(a.Jb[1]), b2 = G(a.Jb[2]);
+            nex -= b0[id];
+            ney -= b1[id];
+            nez -= b2[id];
+            b0[id] = 0.f;
+            b1[id] = 0.f;
+            b2[id] = 0.f;
         }
     }
     const bool wx = !a.per[0] && i == 0, wy = !a.per[1] && j == 0, wz = !a.per[2] && k == 0;
     if (!(wy || wz)) st_once(a.E[0] + id, nex);
     if (!(wx || wz)) st_once(a.E[1] + id, ney);
     if (!(wx || wy)) st_once(a.E[2] + id, nez);
-    if (!(isfinite(nex) && isfinite(ney) && isfinite(nez))) atomicOr(a.nan_flag, 1);
+    if (!(isfinite(nex) && isfinite(ney) && isfinite(nez)))
+        __hip_atomic_fetch_or(G(a.nan_flag), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Decompose a tile index of one simulation into (i, j, k); false when the
@@ -281,8 +287,8 @@ __global__ __launch_bounds__(TXW *TYW) void k_h_update(FieldArgs a)
 {
     int i, j, k;
     if (!tile_cell<TXW, TYW, ZO>(a, xcd_tile(), i, j, k)) return;
-    const DevState s = *a.st;
-    h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
+    const gp<const DevState> st = G(a.st);
+    h_cell(a, st->parity, box_margin(st->since_sort, a.S), i, j, k);
 }
 
 template <int TXW, int TYW, int ZO>
@@ -290,33 +296,42 @@ __global__ __launch_bounds__(TXW *TYW) void k_e_update(FieldArgs a)
 {
     int i, j, k;
     if (!tile_cell<TXW, TYW, ZO>(a, xcd_tile(), i, j, k)) return;
-    const DevState s = *a.st;
-    e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
+    const gp<const DevState> st = G(a.st);
+    e_cell(a, st->parity, box_margin(st->since_sort, a.S), i, j, k);
 }
 
-// Work unit t of a batched launch belongs to simulation own[t] >> 24 as its
-// own unit own[t] & 0xffffff (a table the host builds: one load per
-// workgroup, whatever the number of simulations).
+// Work unit u of a batched launch belongs to simulation own[u] >> 24 as its
+// own unit own[u] & 0xffffff (a table the host builds: one load per
+// workgroup, whatever the number of simulations), which covers that
+// simulation's tiles BATCH_TILES * unit onwards, x-neighbours first.
 template <int TXW, int TYW, int ZO>
-__global__ __launch_bounds__(TXW *TYW) void k_h_update_batch(const FieldArgs *args, const int *own)
+__global__ __launch_bounds__(TXW *TYW) void k_h_update_batch(const FieldArgs *__restrict__ args,
+                                                             const int *__restrict__ own)
 {
     const int o = own[xcd_tile()];
     const FieldArgs &a = args[o >> 24];
-    int i, j, k;
-    if (!tile_cell<TXW, TYW, ZO>(a, o & 0xffffff, i, j, k)) return;
-    const DevState s = *a.st;
-    h_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
+    const gp<const DevState> st = G(a.st);
+    const int parity = st->parity, margin = box_margin(st->since_sort, a.S);
+    const int t0 = (o & 0xffffff) * BATCH_TILES, nt = a.gx * a.gy * a.nz;
+    for (int q = 0; q < BATCH_TILES && t0 + q < nt; ++q) {
+        int i, j, k;
+        if (tile_cell<TXW, TYW, ZO>(a, t0 + q, i, j, k)) h_cell(a, parity, margin, i, j, k);
+    }
 }
 
 template <int TXW, int TYW, int ZO>
-__global__ __launch_bounds__(TXW *TYW) void k_e_update_batch(const FieldArgs *args, const int *own)
+__global__ __launch_bounds__(TXW *TYW) void k_e_update_batch(const FieldArgs *__restrict__ args,
+                                                             const int *__restrict__ own)
 {
     const int o = own[xcd_tile()];
     const FieldArgs &a = args[o >> 24];
-    int i, j, k;
-    if (!tile_cell<TXW, TYW, ZO>(a, o & 0xffffff, i, j, k)) return;
-    const DevState s = *a.st;
-    e_cell(a, s.parity, box_margin(s.since_sort, a.S), i, j, k);
+    const gp<const DevState> st = G(a.st);
+    const int parity = st->parity, margin = box_margin(st->since_sort, a.S);
+    const int t0 = (o & 0xffffff) * BATCH_TILES, nt = a.gx * a.gy * a.nz;
+    for (int q = 0; q < BATCH_TILES && t0 + q < nt; ++q) {
+        int i, j, k;
+        if (tile_cell<TXW, TYW, ZO>(a, t0 + q, i, j, k)) e_cell(a, parity, margin, i, j, k);
+    }
 }
 
 // One launch of a tile-shape instantiation: the shape index selects the

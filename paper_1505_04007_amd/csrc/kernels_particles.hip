@@ -99,11 +99,12 @@ __device__ __forceinline__ void x_pairs(float x, int nx, XPair &P)
     }
 }
 
+// dword-aligned 8-byte global load
+typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 __device__ __forceinline__ float2 ld2(const float *p)
 {
-    float2 v;
-    __builtin_memcpy(&v, p, 8);  // dword-aligned 8-byte global load
-    return v;
+    const float2_a4 v = *(gp<const float2_a4>)G(p);
+    return make_float2(v.x, v.y);
 }
 
 // Trilinear value of a component that sits at half nodes along the axes
@@ -140,7 +141,7 @@ __device__ __forceinline__ float gather_scalar(const float *__restrict__ f, cons
                               (c ? Z.o1[HZ] : Z.o0[HZ]);
                 const float w = (q ? X.m1[HX] : X.m0[HX]) * (b ? Y.m1[HY] : Y.m0[HY]) *
                                 (c ? Z.m1[HZ] : Z.m0[HZ]);
-                v += w * f[o];
+                v += w * G(f)[o];
             }
     return v;
 }
@@ -261,7 +262,7 @@ __device__ __forceinline__ float *slot_addr(const PartArgs &a, int s, int bx, in
 __device__ __forceinline__ void add_fixed(const PartArgs &a, int comp, int q, int units)
 {
     unsigned long long *J = comp == 0 ? a.Jq[0] : (comp == 1 ? a.Jq[1] : a.Jq[2]);
-    atomicAdd(J + q, (unsigned long long)(long long)units);
+    gatomic_add(G(J) + q, (unsigned long long)(long long)units);
 }
 
 // Sum of two slot values: FP32, or the int32 fixed-point units held in the
@@ -468,7 +469,7 @@ __device__ __forceinline__ void union_flush(float *J, const float *plus, const f
         float v = 0.f;
 #pragma unroll
         for (int a = 0; a < NA; ++a) v += pv[it][a] - mv[it][a];
-        if (e < N && v != 0.f) atomicAdd(J + base + t + sy * (r / NZ) + sz * (r % NZ), v);
+        if (e < N && v != 0.f) gatomic_add(G(J) + base + t + sy * (r / NZ) + sz * (r % NZ), v);
     }
 }
 
@@ -514,13 +515,13 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
 {
     const int p = blk * PUSH_BLOCK + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const int pc = a.st->pcur;
-    float *__restrict__ X = a.P[pc][0];
-    float *__restrict__ Y = a.P[pc][1];
-    float *__restrict__ Z = a.P[pc][2];
-    float *__restrict__ UX = a.P[pc][3];
-    float *__restrict__ UY = a.P[pc][4];
-    float *__restrict__ UZ = a.P[pc][5];
+    const int pc = G(a.st)->pcur;
+    const gp<float> __restrict__ X = G(a.P[pc][0]);
+    const gp<float> __restrict__ Y = G(a.P[pc][1]);
+    const gp<float> __restrict__ Z = G(a.P[pc][2]);
+    const gp<float> __restrict__ UX = G(a.P[pc][3]);
+    const gp<float> __restrict__ UY = G(a.P[pc][4]);
+    const gp<float> __restrict__ UZ = G(a.P[pc][5]);
     bool dep = false;
     // zeroed: a lane that does not deposit is silenced by a factor 0 in the
     // wavefront sum, and 0 x (uninitialised register) could be NaN
@@ -612,7 +613,7 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
     }
     const unsigned long long live = __ballot(dep);
     // per-wavefront push counter (one slot per wavefront of the launch)
-    if (lane == 0 && live) a.pushes[p >> 6] += (unsigned long long)__popcll(live);
+    if (lane == 0 && live) G(a.pushes)[p >> 6] += (unsigned long long)__popcll(live);
     unsigned long long rem = live;
     if (MODE == 0 && !FIX && live) {
         // one grid row of windows spanning at least two x bases: the row-union tiles
@@ -672,7 +673,7 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                     if (q >= 0) add_fixed(a, comp, q, __float_as_int(tot));
                 } else {
                     float *ad = inside ? Jl + (bx + a.nx * (by + a.ny * bz)) + lrel : slot_addr(a, lane, bx, by, bz);
-                    if (ad) atomicAdd(ad, tot);
+                    if (ad) gatomic_add(G(ad), tot);
                 }
             }
         }
@@ -695,7 +696,7 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                     if (u != 0) add_fixed(a, comp, lin + (oi + sy * oj + sz * ok), u);
                 } else {
                     float *J = comp == 0 ? a.Jb[0] : (comp == 1 ? a.Jb[1] : a.Jb[2]);
-                    if (v != 0.f) atomicAdd(J + lin + (oi + sy * oj + sz * ok), v);
+                    if (v != 0.f) gatomic_add(G(J) + lin + (oi + sy * oj + sz * ok), v);
                 }
             }
         } else {
@@ -709,7 +710,7 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                     if (q >= 0) add_fixed(a, comp, q, u);
                 } else if (v != 0.f) {
                     float *ad = slot_addr(a, s, base[0], base[1], base[2]);
-                    if (ad) atomicAdd(ad, v);
+                    if (ad) gatomic_add(G(ad), v);
                 }
             }
         }

@@ -118,7 +118,7 @@ pic_status batch_upload_fields(pic_batch *b, int shape)
         fa[q].tile = shape;
         fa[q].gx = (c->n[0] + pic::TILE_FX[shape] - 1) / pic::TILE_FX[shape];
         fa[q].gy = (c->n[1] + pic::TILE_FY[shape] - 1) / pic::TILE_FY[shape];
-        tiles[q] = pic::field_tiles(c->n[0], c->n[1], c->n[2], shape);
+        tiles[q] = pic::batch_field_units(c->n[0], c->n[1], c->n[2], shape);
         if (tiles[q] >= (1LL << 24)) return bfail(b, PIC_EINVAL, "member %d has too many field tiles for a batch", q);
     }
     const std::vector<int> tab = unit_table(tiles);
@@ -201,7 +201,7 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
     // rewrites it in place
     for (int v = 0; v < pic::N_TILE_SHAPES; ++v) {
         long long t = 0;
-        for (pic_ctx *c : b->ctx) t += pic::field_tiles(c->n[0], c->n[1], c->n[2], v);
+        for (pic_ctx *c : b->ctx) t += pic::batch_field_units(c->n[0], c->n[1], c->n[2], v);
         if (t > INT_MAX) return bfail(b, PIC_EINVAL, "too many field tiles in the batch for one launch");
         b->tiles_cap = std::max(b->tiles_cap, (size_t)t);
     }

@@ -40,6 +40,10 @@ constexpr int N_TILE_SHAPES = 16;
 constexpr int TILE_FX[N_TILE_SHAPES] = {64, 64, 128, 256, 32, 64, 128, 32, 64, 64, 128, 256, 32, 64, 128, 32};
 constexpr int TILE_FY[N_TILE_SHAPES] = {4, 2, 2, 1, 8, 8, 4, 4, 4, 2, 2, 1, 8, 8, 4, 4};
 constexpr int TILE_ZO[N_TILE_SHAPES] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1};
+// A batched field launch gives each workgroup this many consecutive tiles of
+// one member: the member lookup (work-unit table, argument block, device
+// state: three dependent loads) is then paid once per four tiles.
+constexpr int BATCH_TILES = 4;
 
 struct DevState {
     int parity;      // H[parity] holds H^{n-1/2} at the start of step n
@@ -169,6 +173,12 @@ inline int field_tiles(int nx, int ny, int nz, int shape = 0)
     return ((nx + fx - 1) / fx) * ((ny + fy - 1) / fy) * nz;
 }
 
+// Work units of one member in a batched field launch.
+inline long long batch_field_units(int nx, int ny, int nz, int shape)
+{
+    return ((long long)field_tiles(nx, ny, nz, shape) + BATCH_TILES - 1) / BATCH_TILES;
+}
+
 // Linear offset to the neighbour at distance d = +-1 along an axis of n
 // cells with stride st: wraps on a periodic axis; across a wall it points
 // at the cell itself and clears `ok` (the neighbour value is then 0).
@@ -179,6 +189,31 @@ __device__ __forceinline__ int nb_off(int i, int d, int n, int per, int st, bool
     ok = in || per;
     const int w = r < 0 ? r + n : r - n;
     return in ? d * st : (per ? (w - i) * st : 0);
+}
+
+// Global-memory pointers.  A pointer the kernels read from device memory (the
+// batched entry points' argument blocks) or pass through a scalar-register
+// pin is generic to the compiler, which then emits flat loads, stores and
+// atomics: 64-bit vector addresses, and counted with the scalar loads, so a
+// wait for either waits for both.  Every pointer the library hands its kernels
+// addresses global memory (the same bits), so accesses go through G(p).
+template <class T>
+using gp = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gp<T> G(T *p)
+{
+    return (gp<T>)p;
+}
+// Two floats as a plain vector (HIP's float2 is a class, which C++ cannot
+// copy out of a global-typed lvalue).
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void gatomic_add(gp<float> p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gatomic_add(gp<unsigned long long> p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Workgroup -> tile with XCD locality: the 8 XCDs receive workgroups round

@@ -32,10 +32,10 @@ HBM_PEAK_GBS = 8000.0
 # wave64 VALU instructions the chip can issue: 256 CUs x 4 SIMDs, one wave64
 # instruction per SIMD every 4 cycles (16 lanes a cycle) at 2.4 GHz
 VALU_PEAK_G = 256 * 4 * 2.4 / 4
-FAMILIES = ("h_update", "push_deposit", "e_update", "probe", "sort")
+FAMILIES = ("h_update", "push_deposit", "e_update", "probe", "sort", "field_sweep")
 KERNEL_SOURCES = {"h_update": "kernels_fields.hip", "e_update": "kernels_fields.hip",
                   "push_deposit": "kernels_particles.hip", "sort": "kernels_particles.hip",
-                  "probe": "kernels_diag.hip"}
+                  "probe": "kernels_diag.hip", "field_sweep": "kernels_fused.hip"}
 
 
 def workload(name):
@@ -75,6 +75,8 @@ def algorithmic_bytes(w, fam, pushes_per_step, pbox):
     e_update : 36 B/cell + 16 B per membership + 32 B per metal-box cell
                (J_pol read + write, (cb, d)) + 24 B per bunch-box cell (J_b read + clear)
     push     : 48 B per live particle (x, u read + write)
+    field_sweep : the one-pass E + H update: 48 B/cell (read E, H; write E,
+               H) + the two updates' CPML, Drude and bunch-current bytes
     """
     N = w.cells
     mem = cpml_memberships(w)
@@ -87,6 +89,9 @@ def algorithmic_bytes(w, fam, pushes_per_step, pbox):
         return 36 * N + 16 * mem + 32 * metal_box_cells(w) + 24 * box
     if fam == "push_deposit":
         return 48 * pushes_per_step
+    if fam == "field_sweep":
+        return (algorithmic_bytes(w, "h_update", pushes_per_step, pbox) +
+                algorithmic_bytes(w, "e_update", pushes_per_step, pbox) - 24 * N)
     return None
 
 
@@ -328,6 +333,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the production, batched and adjoint legs of the default line")
     ap.add_argument("--deposit-mode", type=int, default=0)
+    ap.add_argument("--field-sweep", type=int, default=0,
+                    help="1: the one-pass E + H field sweep instead of the separate launches")
     ap.add_argument("--sort-every", type=int, default=None,
                     help="override the workload's cell-sort interval")
     ap.add_argument("--no-tune", action="store_true",
@@ -370,7 +377,7 @@ def main():
     torch.cuda.set_device(0)
     if args.sort_every is not None:
         w.sort_every = args.sort_every
-    sim = native.from_workload(w, timing=True, deposit_mode=args.deposit_mode)
+    sim = native.from_workload(w, timing=True, deposit_mode=args.deposit_mode, field_sweep=args.field_sweep)
     tune = sim.tune(force=0) if args.no_tune else sim.tune(reps=10)
     if not args.no_tune:
         print("[bench] tile variants ms per H+E pair: " + " ".join(f"{m:.3f}" for m in tune["ms"]),
@@ -468,7 +475,8 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": w.name, "cells": w.cells,
                       "particles": w.bunch.n if w.bunch else 0, "sort_every": w.sort_every,
-                      "deposit_mode": args.deposit_mode, "field_tile": [tune["fx"], tune["fy"], tune["order"]],
+                      "deposit_mode": args.deposit_mode, "field_sweep": args.field_sweep,
+                      "field_tile": [tune["fx"], tune["fy"], tune["order"]],
                       "parallelism": "single-gpu"},
            "particle_pushes_per_s": round(pushes / secs, 1),
            "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}

@@ -140,6 +140,14 @@ typedef struct {
                                  runs are bitwise reproducible; not in batches, nor in
                                  pic_grad with checkpoints) */
     const pic_device_buffers *bufs;  /* optional caller device memory for E and H; NULL = none */
+    int32_t field_sweep;      /* 0: the separate H and E launches (the default, faster on
+                                 the grids measured); 1: pic_step fuses each step's E update
+                                 with the next step's H update into one pass over the grid
+                                 where it can (deposit modes 0 and 1, nx <= 1024, each of E,
+                                 H[0], H[1] one block with its components nx*ny*nz apart),
+                                 with the same bits as the separate launches, keeping a
+                                 second copy of E, J_pol and the E-side CPML memories on the
+                                 device */
 } pic_opts;
 
 typedef struct pic_ctx pic_ctx;
@@ -338,8 +346,9 @@ pic_status pic_stats(pic_ctx *ctx, pic_stats_out *out);
 /*
  * Per-kernel device time (opts.timing = 1), measured with HIP events on the
  * context's stream.  names: kernel families in order
- *   0 h_update, 1 push_deposit, 2 e_update, 3 probe, 4 sort.
- * ms_total[5], launches[5] receive the accumulated milliseconds and launch
+ *   0 h_update, 1 push_deposit, 2 e_update, 3 probe, 4 sort,
+ *   5 field_sweep (the one-pass E + H update, with its clear of the bunch current).
+ * ms_total[6], launches[6] receive the accumulated milliseconds and launch
  * counts since init or the last reset; reset = 1 clears them afterwards.
  * The context holds two HIP events per timed launch until a reset: in a
  * long timed run, call with reset = 1 from time to time.

@@ -11,8 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["pic_abi.hip", "pic_grad.hip", "pic_batch.hip", "kernels_fields.hip", "kernels_particles.hip", "kernels_diag.hip",
-           "kernels_adjoint.hip"]
+SOURCES = ["pic_abi.hip", "pic_grad.hip", "pic_batch.hip", "kernels_fields.hip", "kernels_fused.hip",
+           "kernels_particles.hip", "kernels_diag.hip", "kernels_adjoint.hip"]
 LIB = os.path.join(PKG, "libpic.so")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-fvisibility=hidden", "-fvisibility-inlines-hidden",

@@ -248,6 +248,108 @@ pic_status step_once(pic_ctx *c)
     return step_body(c, nullptr);
 }
 
+// ---- one-pass field sweep ----
+
+// Point the context's E-side arrays at block e and rebuild the argument blocks.
+static void set_e_side(pic_ctx *c, int e)
+{
+    c->ecur = e;
+    const size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
+    for (int d = 0; d < 3; ++d) {
+        c->E[d] = c->Eb[e] + d * N;
+        if (c->Jpb[e]) c->Jp[d] = c->Jpb[e] + d * c->nbox;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (c->psiEb[a][e])
+            for (int q = 0; q < 2; ++q) c->pml[a].psiE[q] = c->psiEb[a][e] + q * c->slab[a];
+    build_args(c);
+}
+
+static pic::FusedArgs fused_args(const pic_ctx *c)
+{
+    pic::FusedArgs a{};
+    a.nx = c->n[0];
+    a.ny = c->n[1];
+    a.nz = c->n[2];
+    a.S = (float)c->S;
+    a.N = c->n[0] * c->n[1] * c->n[2];
+    const int e = c->ecur;
+    a.Ein = c->Eb[e];
+    a.Eout = c->Eb[e ^ 1];
+    a.Hin = c->H[c->hcur ^ 1][0];  // H^{n+1/2}, from this step's H update
+    a.Hout = c->H[c->hcur][0];     // over H^{n-1/2}
+    a.Havg = c->np > 0 ? c->Havg[0] : nullptr;
+    for (int d = 0; d < 3; ++d) {
+        a.per[d] = c->per[d];
+        a.pon[d] = c->pml[d].on;
+        a.npml[d] = c->pml[d].npml;
+        a.tab[d] = c->pml[d].bE;  // bE cE kE bH cH kH, n apart
+        a.slab[d] = (int)c->slab[d];
+        a.psiEin[d] = c->psiEb[d][e];
+        a.psiEout[d] = c->psiEb[d][e ^ 1];
+        a.psiH[d] = c->pml[d].psiH[0];
+        a.mlo[d] = c->has_metal ? c->mlo[d] : 0;
+        a.mhi[d] = c->has_metal ? c->mhi[d] : 0;
+    }
+    a.nbox = (int)c->nbox;
+    a.Jpin = c->Jpb[e];
+    a.Jpout = c->Jpb[e ^ 1];
+    a.coef = c->coef;
+    a.Jb = c->np > 0 ? c->Jb[0] : nullptr;
+    a.pbox = c->np > 0 ? c->box : nullptr;
+    a.nan_flag = c->d_nan;
+    a.st = c->dstate;
+    a.gy = (c->n[1] + pic::FUSED_ROWS - 1) / pic::FUSED_ROWS;
+    return a;
+}
+
+// A step whose H update the previous sweep (or the chain's start) made:
+// the sort when due (not for the chain's first step, sorted before its H
+// update), the push, then either the sweep (this step's E update and the
+// next step's H update) or this step's E update alone, then the probes.
+static pic_status chain_step(pic_ctx *c, bool sweep, bool first)
+{
+    if (!first && c->np > 0 && c->sort_every > 0 && c->since_sort >= c->sort_every) TRY(do_sort(c));
+    if (c->np > 0) {
+        tstart(c, 1);
+        pic::launch_push_deposit(c->pa, c->deposit_mode, c->stream);
+        tstop(c, 1);
+    }
+    if (sweep) {
+        tstart(c, 5);
+        pic::launch_fused(fused_args(c), c->stream);
+        if (c->np > 0)
+            pic::launch_jb_clear(c->Jb[0], c->n[0] * c->n[1] * c->n[2], c->n[0], c->n[1], c->n[2], c->per, c->box,
+                                 (float)c->S, c->dstate, c->stream);
+        tstop(c, 5);
+        set_e_side(c, c->ecur ^ 1);  // the probes read the new E
+    } else {
+        tstart(c, 2);
+        pic::launch_e_update(c->fa, c->stream);
+        tstop(c, 2);
+    }
+    tstart(c, 3);
+    pic::launch_probe(c->pr, c->stream);
+    tstop(c, 3);
+    c->hcur = 1 - c->hcur;
+    c->step++;
+    c->since_sort++;
+    HIP_TRY(c, hipGetLastError());
+    return PIC_OK;
+}
+
+// The non-finite poll of pic_step.
+static pic_status poll_nan(pic_ctx *c)
+{
+    if (c->check_every > 0 && c->step % c->check_every == 0) {
+        int flag = 0;
+        HIP_TRY(c, hipMemcpyAsync(&flag, c->d_nan, 4, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (flag) return fail(c, PIC_EUNSTABLE, "non-finite field value detected by step %lld", c->step);
+    }
+    return PIC_OK;
+}
+
 pic::DiagArgs diag_args(pic_ctx *c)
 {
     pic::DiagArgs a{};
@@ -305,6 +407,25 @@ void pic_destroy(pic_ctx *ctx)
     delete ctx;
 }
 
+// The one-pass field sweep (asked for with field_sweep = 1) needs a
+// workgroup to span x, the FP32 bunch
+// current, and each of E, H[0], H[1] as one block with components N apart
+// (any the caller gives must already be laid out so).
+static bool fused_eligible(const pic_grid &g, const pic_opts &o)
+{
+    if (o.field_sweep != 1 || o.deposit_mode == 2 || g.nx > 1024) return false;
+    if (o.bufs) {
+        const size_t N = (size_t)g.nx * g.ny * g.nz;
+        for (int f = 0; f < 3; ++f) {
+            float *const *p = f == 0 ? o.bufs->E : o.bufs->H[f - 1];
+            const int given = (p[0] != nullptr) + (p[1] != nullptr) + (p[2] != nullptr);
+            if (given == 0) continue;
+            if (given != 3 || p[1] != p[0] + N || p[2] != p[0] + 2 * N) return false;
+        }
+    }
+    return true;
+}
+
 static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double dt,
                             const double *wp_map, const double *gamma_map,
                             const pic_particles *parts, const pic_opts *opts)
@@ -359,6 +480,8 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
     if (o.deposit_mode < 0 || o.deposit_mode > 2)
         return fail(c, PIC_EINVAL, "deposit_mode = %d is not 0, 1 or 2", o.deposit_mode);
     c->deposit_mode = o.deposit_mode;
+    if (o.field_sweep < 0 || o.field_sweep > 1)
+        return fail(c, PIC_EINVAL, "field_sweep = %d is not 0 or 1", o.field_sweep);
     if (o.nprobe < 0 || o.nfreq < 0 || o.series_len < 0)
         return fail(c, PIC_EINVAL, "nprobe, nfreq and series_len must be >= 0");
     if (o.nprobe > 256) return fail(c, PIC_EINVAL, "at most 256 probes");
@@ -401,19 +524,35 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
                     return fail(c, PIC_EINVAL, "bufs: field arrays %d and %d overlap", r, q);
         }
     }
-    for (int d = 0; d < 3; ++d) {
-        float *gE = o.bufs ? o.bufs->E[d] : nullptr;
-        float *gH0 = o.bufs ? o.bufs->H[0][d] : nullptr;
-        float *gH1 = o.bufs ? o.bufs->H[1][d] : nullptr;
-        if (gE) c->E[d] = gE;
-        else TRY(dalloc(c, &c->E[d], N));
-        if (gH0) c->H[0][d] = gH0;
-        else TRY(dalloc(c, &c->H[0][d], N));
-        if (gH1) c->H[1][d] = gH1;
-        else TRY(dalloc(c, &c->H[1][d], N));
-        HIP_TRY(c, hipMemsetAsync(c->E[d], 0, N * 4, c->stream));
-        HIP_TRY(c, hipMemsetAsync(c->H[0][d], 0, N * 4, c->stream));
-        HIP_TRY(c, hipMemsetAsync(c->H[1][d], 0, N * 4, c->stream));
+    // each field the library allocates is one block, its components N apart
+    // (the one-pass sweep addresses them from one base)
+    {
+        float *blk[3] = {nullptr, nullptr, nullptr};  // E, H[0], H[1]
+        for (int f = 0; f < 3; ++f) {
+            bool any = false;
+            for (int d = 0; d < 3; ++d) {
+                float *g = o.bufs ? (f == 0 ? o.bufs->E[d] : o.bufs->H[f - 1][d]) : nullptr;
+                any = any || g;
+            }
+            if (!any) TRY(dalloc(c, &blk[f], 3 * N));
+        }
+        for (int d = 0; d < 3; ++d) {
+            float *gE = o.bufs ? o.bufs->E[d] : nullptr;
+            float *gH0 = o.bufs ? o.bufs->H[0][d] : nullptr;
+            float *gH1 = o.bufs ? o.bufs->H[1][d] : nullptr;
+            if (gE) c->E[d] = gE;
+            else if (blk[0]) c->E[d] = blk[0] + d * N;
+            else TRY(dalloc(c, &c->E[d], N));
+            if (gH0) c->H[0][d] = gH0;
+            else if (blk[1]) c->H[0][d] = blk[1] + d * N;
+            else TRY(dalloc(c, &c->H[0][d], N));
+            if (gH1) c->H[1][d] = gH1;
+            else if (blk[2]) c->H[1][d] = blk[2] + d * N;
+            else TRY(dalloc(c, &c->H[1][d], N));
+            HIP_TRY(c, hipMemsetAsync(c->E[d], 0, N * 4, c->stream));
+            HIP_TRY(c, hipMemsetAsync(c->H[0][d], 0, N * 4, c->stream));
+            HIP_TRY(c, hipMemsetAsync(c->H[1][d], 0, N * 4, c->stream));
+        }
     }
     TRY(dalloc(c, &c->d_nan, 1));
     HIP_TRY(c, hipMemsetAsync(c->d_nan, 0, 4, c->stream));
@@ -498,10 +637,10 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         TRY(dalloc(c, &c->coef, nb));
         stage.emplace_back(std::move(cf));
         TRY(upload(c->coef, stage.back().data(), 2 * nb * 4));
-        for (int d = 0; d < 3; ++d) {
-            TRY(dalloc(c, &c->Jp[d], nb));
-            HIP_TRY(c, hipMemsetAsync(c->Jp[d], 0, nb * 4, c->stream));
-        }
+        float *jblk = nullptr;
+        TRY(dalloc(c, &jblk, 3 * nb));
+        HIP_TRY(c, hipMemsetAsync(jblk, 0, 3 * nb * 4, c->stream));
+        for (int d = 0; d < 3; ++d) c->Jp[d] = jblk + d * nb;
     }
 
     // CPML tables and psi slabs
@@ -528,11 +667,14 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         P.cH = dtab + 4 * n;
         P.kH = dtab + 5 * n;
         const size_t slab = (size_t)2 * g.npml * (N / (size_t)n);
+        float *pe = nullptr, *ph = nullptr;
+        TRY(dalloc(c, &pe, 2 * slab));
+        TRY(dalloc(c, &ph, 2 * slab));
+        HIP_TRY(c, hipMemsetAsync(pe, 0, 2 * slab * 4, c->stream));
+        HIP_TRY(c, hipMemsetAsync(ph, 0, 2 * slab * 4, c->stream));
         for (int q = 0; q < 2; ++q) {
-            TRY(dalloc(c, &P.psiE[q], slab));
-            TRY(dalloc(c, &P.psiH[q], slab));
-            HIP_TRY(c, hipMemsetAsync(P.psiE[q], 0, slab * 4, c->stream));
-            HIP_TRY(c, hipMemsetAsync(P.psiH[q], 0, slab * 4, c->stream));
+            P.psiE[q] = pe + q * slab;
+            P.psiH[q] = ph + q * slab;
         }
     }
 
@@ -635,12 +777,18 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
             if (c->deposit_mode == 2) {
                 TRY(dalloc(c, &c->Jq[d], N));
                 HIP_TRY(c, hipMemsetAsync(c->Jq[d], 0, N * 8, c->stream));
-            } else {
-                TRY(dalloc(c, &c->Jb[d], N));
-                HIP_TRY(c, hipMemsetAsync(c->Jb[d], 0, N * 4, c->stream));
             }
-            TRY(dalloc(c, &c->Havg[d], N));
-            HIP_TRY(c, hipMemsetAsync(c->Havg[d], 0, N * 4, c->stream));
+        }
+        float *jb = nullptr, *hv = nullptr;
+        if (c->deposit_mode != 2) {
+            TRY(dalloc(c, &jb, 3 * N));
+            HIP_TRY(c, hipMemsetAsync(jb, 0, 3 * N * 4, c->stream));
+        }
+        TRY(dalloc(c, &hv, 3 * N));
+        HIP_TRY(c, hipMemsetAsync(hv, 0, 3 * N * 4, c->stream));
+        for (int d = 0; d < 3; ++d) {
+            if (jb) c->Jb[d] = jb + d * N;
+            c->Havg[d] = hv + d * N;
         }
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         build_args(c);
@@ -654,6 +802,25 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
             a.rho = c->rho0;
             pic::launch_rho(a, c->stream);
             HIP_TRY(c, hipGetLastError());
+        }
+    }
+    if (fused_eligible(g, o)) {
+        // second blocks of the E-side state for the one-pass sweep
+        c->fused = true;
+        c->Eb[0] = c->E[0];
+        TRY(dalloc(c, &c->Eb[1], 3 * N));
+        HIP_TRY(c, hipMemsetAsync(c->Eb[1], 0, 3 * N * 4, c->stream));
+        if (c->has_metal) {
+            c->Jpb[0] = c->Jp[0];
+            TRY(dalloc(c, &c->Jpb[1], 3 * c->nbox));
+            HIP_TRY(c, hipMemsetAsync(c->Jpb[1], 0, 3 * c->nbox * 4, c->stream));
+        }
+        for (int d = 0; d < 3; ++d) {
+            if (!c->pml[d].on) continue;
+            c->slab[d] = (size_t)2 * g.npml * (N / (size_t)nn[d]);
+            c->psiEb[d][0] = c->pml[d].psiE[0];
+            TRY(dalloc(c, &c->psiEb[d][1], 2 * c->slab[d]));
+            HIP_TRY(c, hipMemsetAsync(c->psiEb[d][1], 0, 2 * c->slab[d] * 4, c->stream));
         }
     }
     build_args(c);
@@ -729,10 +896,17 @@ pic_status pic_query_sizes(const pic_grid *grid, int64_t nparticles, const pic_o
         total += 3 * bytes(N, 4);                             // time-centred H
         if (o.diag) total += 2 * bytes((n[0] + 1) * (n[1] + 1) * (n[2] + 1), 8);
     }
+    const bool fused = fused_eligible(g, o);
+    if (fused) {                                              // the sweep's second E-side blocks
+        total += bytes(3 * N, 4);
+        for (int d = 0; d < 3; ++d)
+            if (g.bc[d] == PIC_BC_CPML) total += bytes(2 * 2LL * g.npml * (N / n[d]), 4);
+    }
     out->field_elems = N;
     out->field_bytes = 4 * N;
     out->device_bytes = total;
-    out->bytes_per_metal_box_cell = sizeof(float2) + 3 * sizeof(float);  // (cbt, d) + J_pol
+    // (cbt, d) + J_pol, and the sweep's second J_pol block
+    out->bytes_per_metal_box_cell = sizeof(float2) + (fused ? 6 : 3) * sizeof(float);
     return PIC_OK;
 }
 
@@ -740,14 +914,28 @@ pic_status pic_step(pic_ctx *c, int64_t nsteps)
 {
     CHECK_CTX(c);
     if (nsteps < 0) return fail(c, PIC_EINVAL, "nsteps must be >= 0");
+    if (c->fused && nsteps >= 3) {
+        // an even number of sweeps, so the E-side blocks end where they began;
+        // the steps before them and the last E update use the separate kernels
+        const int64_t sweeps = (nsteps - 1) & ~1LL;
+        for (int64_t it = 0; it < nsteps - 1 - sweeps; ++it) {
+            TRY(step_once(c));
+            TRY(poll_nan(c));
+        }
+        if (c->np > 0 && c->sort_every > 0 && c->since_sort >= c->sort_every) TRY(do_sort(c));
+        tstart(c, 0);
+        pic::launch_h_update(c->fa, c->stream);
+        tstop(c, 0);
+        for (int64_t m = 0; m < sweeps; ++m) {
+            TRY(chain_step(c, true, m == 0));
+            TRY(poll_nan(c));
+        }
+        TRY(chain_step(c, false, false));
+        return poll_nan(c);
+    }
     for (int64_t it = 0; it < nsteps; ++it) {
         TRY(step_once(c));
-        if (c->check_every > 0 && c->step % c->check_every == 0) {
-            int flag = 0;
-            HIP_TRY(c, hipMemcpyAsync(&flag, c->d_nan, 4, hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            if (flag) return fail(c, PIC_EUNSTABLE, "non-finite field value detected by step %lld", c->step);
-        }
+        TRY(poll_nan(c));
     }
     return PIC_OK;
 }

@@ -21,7 +21,7 @@ constexpr double kC = 299792458.0;
 constexpr double kMu0 = 1.25663706212e-6;
 constexpr double kEps0 = 1.0 / (kMu0 * kC * kC);
 constexpr double kEta0 = kMu0 * kC;
-constexpr int kFamilies = 5;  // h_update, push_deposit, e_update, probe, sort
+constexpr int kFamilies = 6;  // h_update, push_deposit, e_update, probe, sort, field_sweep
 
 }  // namespace pich
 
@@ -94,6 +94,16 @@ struct pic_ctx {
 
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[pich::kFamilies];
+
+    // one-pass field sweep: the E-side state (E, J_pol, E-side CPML
+    // memories) in two blocks each, ecur the one holding the current values;
+    // every pic_step call ends with ecur = 0, the blocks pic_init set up
+    bool fused = false;
+    float *Eb[2] = {nullptr, nullptr};          // [3N]
+    float *Jpb[2] = {nullptr, nullptr};         // [3 nbox]
+    float *psiEb[3][2] = {};                    // per CPML axis [2 slab]
+    size_t slab[3] = {0, 0, 0};                 // psi cells per component of an axis
+    int ecur = 0;
 
     // this device's address of the library's static gradient scratch (bound at
     // pic_init), or null with the reason in sscratch_err

@@ -97,6 +97,41 @@ struct FieldArgs {
     DevState *st;
 };
 
+// One-pass field sweep (E update of step n, then H update of step n + 1).
+// Every field is one block with its components FIELD_STRIDE apart; the E-side
+// state (E, J_pol, the E-side CPML memories) is read from the *in blocks and
+// written to the *out blocks, since a workgroup recomputes its neighbours'
+// new E at its edges from their old values.
+constexpr int FUSED_ROWS = 4;    // y rows per lane
+constexpr int FUSED_PLANES = 16;  // z planes per workgroup
+struct FusedArgs {
+    int nx, ny, nz;
+    int per[3];
+    float S;
+    int N;                       // cells: component stride of E, H, Havg, J_b
+    const float *Ein;            // [3][N] E^n
+    float *Eout;                 // [3][N] E^{n+1}
+    const float *Hin;            // [3][N] H^{n+1/2}
+    float *Hout;                 // [3][N] H^{n+3/2}
+    float *Havg;                 // [3][N] (H^{n+1/2} + H^{n+3/2}) / 2 in the particle box, or null
+    int pon[3], npml[3];
+    const float *tab[3];         // per axis [6][n]: bE, cE, kE, bH, cH, kH
+    int slab[3];                 // psi cells per component of an axis
+    const float *psiEin[3];      // per axis [2][slab]
+    float *psiEout[3];
+    float *psiH[3];              // updated in place (one owner per H cell)
+    int mlo[3], mhi[3];          // metal box [lo, hi)
+    int nbox;                    // metal-box cells: component stride of J_pol
+    const float *Jpin;           // [3][nbox] J_pol^{n-1/2}
+    float *Jpout;                // [3][nbox] J_pol^{n+1/2}
+    const float2 *coef;          // (cbt, d) per metal-box cell
+    const float *Jb;             // [3][N] bunch current, or null (read only: cleared afterwards)
+    const int *pbox;             // device [6] live-cell box of the last sort, or null
+    int *nan_flag;
+    DevState *st;
+    int gy;                      // y blocks of FUSED_ROWS rows
+};
+
 struct PartArgs {
     int n;
     float *P[2][6];  // x, y, z, ux, uy, uz for each buffer set
@@ -230,6 +265,9 @@ __device__ __forceinline__ int xcd_tile()
 __device__ __forceinline__ int slab_p(int q, int n, int np) { return q < np ? q : q - (n - 2 * np); }
 
 // launchers (stream-ordered, no synchronisation)
+void launch_fused(const FusedArgs &a, hipStream_t s);
+void launch_jb_clear(float *Jb, int N, int nx, int ny, int nz, const int *per, const int *pbox, float S,
+                     const DevState *st, hipStream_t s);
 void launch_h_update(const FieldArgs &a, hipStream_t s);
 void launch_e_update(const FieldArgs &a, hipStream_t s);
 void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s);

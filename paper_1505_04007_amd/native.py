@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVIC
                 -4: "PIC_EUNSTABLE", -5: "PIC_ESTATE", -6: "PIC_ENOTSUP"}
 BC_PEC, BC_PERIODIC, BC_CPML = 0, 1, 2
 FIELD_E, FIELD_H, FIELD_JPOL, FIELD_JB = 0, 1, 2, 3
-KERNEL_FAMILIES = ("h_update", "push_deposit", "e_update", "probe", "sort")
+KERNEL_FAMILIES = ("h_update", "push_deposit", "e_update", "probe", "sort", "field_sweep")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -47,7 +47,7 @@ class PicOpts(ctypes.Structure):
                 ("sort_every", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("init_E", _dp * 3), ("init_H", _dp * 3), ("diag", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("deposit_mode", ctypes.c_int32),
-                ("bufs", ctypes.POINTER(PicDeviceBuffers))]
+                ("bufs", ctypes.POINTER(PicDeviceBuffers)), ("field_sweep", ctypes.c_int32)]
 
 
 class PicDiag(ctypes.Structure):
@@ -198,7 +198,7 @@ class Simulation:
     def __init__(self, nx, ny, nz, dx, dt, wp_map, gamma_map, bc=(BC_PEC,) * 3, npml=0,
                  pml=(3.0, 1.0, 1.0, 0.0), bunch=None, probes=None, omega=None, series_len=0,
                  sort_every=0, check_every=0, init_E=None, init_H=None, diag=False, timing=False,
-                 deposit_mode=0, device_fields=False, stream=None):
+                 deposit_mode=0, device_fields=False, stream=None, field_sweep=0):
         self._lib = load()
         self._E_dev = self._H_dev = None
         self.n = (int(nx), int(ny), int(nz))
@@ -242,6 +242,7 @@ class Simulation:
         o.diag = int(bool(diag))
         o.timing = int(bool(timing))
         o.deposit_mode = int(deposit_mode)
+        o.field_sweep = int(field_sweep)
         if device_fields:
             import torch
             shape = (int(nz), int(ny), int(nx))
@@ -391,23 +392,27 @@ def spp_power(make_sim, omega0, nsteps, ckpt_every=0):
 
 
 def query_sizes(nx, ny, nz, bc=(BC_PEC,) * 3, npml=0, pml=(3.0, 1.0, 1.0, 0.0), nparticles=0,
-                nprobe=0, nfreq=0, series_len=0, diag=False, device_fields=False, deposit_mode=0):
+                nprobe=0, nfreq=0, series_len=0, diag=False, device_fields=False, deposit_mode=0,
+                field_sweep=0):
     """pic_query_sizes: device memory pic_init needs (a dict of pic_buffer_sizes).
 
     device_fields=True counts E and H as caller memory (as Simulation(...,
-    device_fields=True) provides them); only whether those entries are set
-    matters to the query, so placeholders stand in for the pointers."""
+    device_fields=True) provides them); the query reads only which entries are
+    set and how they are laid out, so placeholders with the layout of those
+    tensors (each field one block, components nx*ny*nz apart) stand in."""
     lib = load()
     g = PicGrid(nx, ny, nz, (ctypes.c_int32 * 3)(*[int(b) for b in bc]), int(npml), *pml)
     o = PicOpts()
     o.nprobe, o.nfreq, o.series_len, o.diag = int(nprobe), int(nfreq), int(series_len), int(bool(diag))
     o.deposit_mode = int(deposit_mode)
+    o.field_sweep = int(field_sweep)
     if device_fields:
+        N = 4 * int(nx) * int(ny) * int(nz)
         bufs = PicDeviceBuffers()
         for d in range(3):
-            bufs.E[d] = 4 * (3 * d + 1)
+            bufs.E[d] = 4096 + d * N
             for p in range(2):
-                bufs.H[p][d] = 4 * (3 * d + 2 + p)
+                bufs.H[p][d] = 4096 + (3 + 3 * p + d) * N
         o.bufs = ctypes.pointer(bufs)
     out = PicBufferSizes()
     st = lib.pic_query_sizes(ctypes.byref(g), int(nparticles), ctypes.byref(o), ctypes.byref(out))

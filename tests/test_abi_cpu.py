@@ -187,21 +187,25 @@ def test_query_sizes_without_a_device():
     """pic_query_sizes answers on the host: per-array sizes, caller-held E and H
     removed from the total, particles adding at least their own state, and
     the same argument checks as pic_init."""
-    q = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
-                           nparticles=0, nprobe=3, nfreq=16)
+    bc = (native.BC_CPML, native.BC_PERIODIC, native.BC_PEC)
+    q = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=0, nprobe=3, nfreq=16)
     N = 40 * 24 * 30
     assert q["field_elems"] == N and q["field_bytes"] == 4 * N
     assert q["bytes_per_metal_box_cell"] == 20
     assert q["device_bytes"] >= 9 * 4 * N
-    own = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
-                             nparticles=0, nprobe=3, nfreq=16, device_fields=True)
+    own = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=0, nprobe=3, nfreq=16, device_fields=True)
     assert q["device_bytes"] - own["device_bytes"] == 9 * 4 * N
-    withp = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
-                               nparticles=1000, nprobe=3, nfreq=16)
+    withp = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=1000, nprobe=3, nfreq=16)
     assert withp["device_bytes"] - q["device_bytes"] >= 1000 * 2 * 7 * 4 + 6 * 4 * N
-    fixed = native.query_sizes(40, 24, 30, bc=(native.BC_CPML, native.BC_PERIODIC, native.BC_PEC), npml=4,
-                               nparticles=1000, nprobe=3, nfreq=16, deposit_mode=2)
-    assert fixed["device_bytes"] - withp["device_bytes"] == 3 * 4 * N  # 64-bit bunch current
+    fixed = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=1000, nprobe=3, nfreq=16, deposit_mode=2)
+    assert fixed["device_bytes"] - withp["device_bytes"] == 3 * 4 * N  # 64-bit bunch current, no sweep
+    # the one-pass sweep: a second E block, and per CPML axis a second block
+    # of the E-side memories (x: 2 * 2 * npml * ny * nz cells)
+    sw = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=1000, nprobe=3, nfreq=16, field_sweep=1)
+    assert sw["device_bytes"] - withp["device_bytes"] == 3 * 4 * N + 2 * 2 * 4 * (N // 40) * 4
+    assert sw["bytes_per_metal_box_cell"] == 32
+    wide = native.query_sizes(1025, 2, 2, nprobe=0, nfreq=0, field_sweep=1)  # x wider than a workgroup: no sweep
+    assert wide["bytes_per_metal_box_cell"] == 20
     for kw, frag in ((dict(nx=2048, ny=1024, nz=1024), "2^31-1"),
                      (dict(bc=(native.BC_CPML,) * 3, npml=20), "npml"),
                      (dict(nparticles=-1), "nparticles")):

@@ -102,7 +102,7 @@ struct FieldArgs {
 // state (E, J_pol, the E-side CPML memories) is read from the *in blocks and
 // written to the *out blocks, since a workgroup recomputes its neighbours'
 // new E at its edges from their old values.
-constexpr int FUSED_ROWS = 4;    // y rows per lane
+constexpr int FUSED_ROWS = 2;    // y rows per lane
 constexpr int FUSED_PLANES = 16;  // z planes per workgroup
 struct FusedArgs {
     int nx, ny, nz;

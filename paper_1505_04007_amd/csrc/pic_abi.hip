@@ -254,9 +254,8 @@ pic_status step_once(pic_ctx *c)
 static void set_e_side(pic_ctx *c, int e)
 {
     c->ecur = e;
-    const size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
     for (int d = 0; d < 3; ++d) {
-        c->E[d] = c->Eb[e] + d * N;
+        c->E[d] = c->Eb[e] + d * c->fs;
         if (c->Jpb[e]) c->Jp[d] = c->Jpb[e] + d * c->nbox;
     }
     for (int a = 0; a < 3; ++a)
@@ -272,7 +271,7 @@ static pic::FusedArgs fused_args(const pic_ctx *c)
     a.ny = c->n[1];
     a.nz = c->n[2];
     a.S = (float)c->S;
-    a.N = c->n[0] * c->n[1] * c->n[2];
+    a.N = (int)c->fs;
     const int e = c->ecur;
     a.Ein = c->Eb[e];
     a.Eout = c->Eb[e ^ 1];
@@ -319,8 +318,8 @@ static pic_status chain_step(pic_ctx *c, bool sweep, bool first)
         tstart(c, 5);
         pic::launch_fused(fused_args(c), c->stream);
         if (c->np > 0)
-            pic::launch_jb_clear(c->Jb[0], c->n[0] * c->n[1] * c->n[2], c->n[0], c->n[1], c->n[2], c->per, c->box,
-                                 (float)c->S, c->dstate, c->stream);
+            pic::launch_jb_clear(c->Jb[0], (int)c->fs, c->n[0], c->n[1], c->n[2], c->per, c->box, (float)c->S,
+                                 c->dstate, c->stream);
         tstop(c, 5);
         set_e_side(c, c->ecur ^ 1);  // the probes read the new E
     } else {
@@ -407,6 +406,40 @@ void pic_destroy(pic_ctx *ctx)
     delete ctx;
 }
 
+// Component stride of the field blocks the library allocates: the cell
+// count plus 1 MiB + 256 B, so that a field's three components do not sit a
+// power of two apart (on a grid of 2^k cells that maps them onto the same
+// HBM channels and slows the streaming kernels by a few per cent).
+constexpr size_t kFieldPad = 262208;
+static size_t field_stride(size_t N) { return N + kFieldPad; }
+
+// The component stride shared by the fields the caller gives: 0 when it gives
+// none, -1 when a given field is not three equally spaced arrays (at least N
+// apart) or two fields differ.
+static long long given_stride(const pic_opts &o, size_t N)
+{
+    if (!o.bufs) return 0;
+    long long st = 0;
+    for (int f = 0; f < 3; ++f) {
+        float *const *p = f == 0 ? o.bufs->E : o.bufs->H[f - 1];
+        const int given = (p[0] != nullptr) + (p[1] != nullptr) + (p[2] != nullptr);
+        if (given == 0) continue;
+        if (given != 3) return -1;
+        const long long s1 = p[1] - p[0], s2 = p[2] - p[1];
+        if (s1 != s2 || s1 < (long long)N || (st && st != s1)) return -1;
+        st = s1;
+    }
+    return st;
+}
+
+// The component stride of the library's own field blocks: the caller's, when
+// it gives fields, so that the one-pass sweep can address them all alike.
+static size_t block_stride(const pic_opts &o, size_t N)
+{
+    const long long g = given_stride(o, N);
+    return g > 0 ? (size_t)g : field_stride(N);
+}
+
 // The one-pass field sweep (asked for with field_sweep = 1) needs a
 // workgroup to span x, the FP32 bunch
 // current, and each of E, H[0], H[1] as one block with components N apart
@@ -414,16 +447,7 @@ void pic_destroy(pic_ctx *ctx)
 static bool fused_eligible(const pic_grid &g, const pic_opts &o)
 {
     if (o.field_sweep != 1 || o.deposit_mode == 2 || g.nx > 1024) return false;
-    if (o.bufs) {
-        const size_t N = (size_t)g.nx * g.ny * g.nz;
-        for (int f = 0; f < 3; ++f) {
-            float *const *p = f == 0 ? o.bufs->E : o.bufs->H[f - 1];
-            const int given = (p[0] != nullptr) + (p[1] != nullptr) + (p[2] != nullptr);
-            if (given == 0) continue;
-            if (given != 3 || p[1] != p[0] + N || p[2] != p[0] + 2 * N) return false;
-        }
-    }
-    return true;
+    return given_stride(o, (size_t)g.nx * g.ny * g.nz) >= 0;
 }
 
 static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double dt,
@@ -524,30 +548,33 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
                     return fail(c, PIC_EINVAL, "bufs: field arrays %d and %d overlap", r, q);
         }
     }
-    // each field the library allocates is one block, its components N apart
-    // (the one-pass sweep addresses them from one base)
+    // for the one-pass sweep each field the library allocates is one block,
+    // its components c->fs apart (the sweep addresses them from one base);
+    // otherwise every component is an allocation of its own
+    const bool blocks = fused_eligible(g, o);
+    c->fs = blocks ? block_stride(o, N) : N;
     {
         float *blk[3] = {nullptr, nullptr, nullptr};  // E, H[0], H[1]
-        for (int f = 0; f < 3; ++f) {
+        for (int f = 0; blocks && f < 3; ++f) {
             bool any = false;
             for (int d = 0; d < 3; ++d) {
-                float *g = o.bufs ? (f == 0 ? o.bufs->E[d] : o.bufs->H[f - 1][d]) : nullptr;
-                any = any || g;
+                float *gv = o.bufs ? (f == 0 ? o.bufs->E[d] : o.bufs->H[f - 1][d]) : nullptr;
+                any = any || gv;
             }
-            if (!any) TRY(dalloc(c, &blk[f], 3 * N));
+            if (!any) TRY(dalloc(c, &blk[f], 2 * c->fs + N));
         }
         for (int d = 0; d < 3; ++d) {
             float *gE = o.bufs ? o.bufs->E[d] : nullptr;
             float *gH0 = o.bufs ? o.bufs->H[0][d] : nullptr;
             float *gH1 = o.bufs ? o.bufs->H[1][d] : nullptr;
             if (gE) c->E[d] = gE;
-            else if (blk[0]) c->E[d] = blk[0] + d * N;
+            else if (blk[0]) c->E[d] = blk[0] + d * c->fs;
             else TRY(dalloc(c, &c->E[d], N));
             if (gH0) c->H[0][d] = gH0;
-            else if (blk[1]) c->H[0][d] = blk[1] + d * N;
+            else if (blk[1]) c->H[0][d] = blk[1] + d * c->fs;
             else TRY(dalloc(c, &c->H[0][d], N));
             if (gH1) c->H[1][d] = gH1;
-            else if (blk[2]) c->H[1][d] = blk[2] + d * N;
+            else if (blk[2]) c->H[1][d] = blk[2] + d * c->fs;
             else TRY(dalloc(c, &c->H[1][d], N));
             HIP_TRY(c, hipMemsetAsync(c->E[d], 0, N * 4, c->stream));
             HIP_TRY(c, hipMemsetAsync(c->H[0][d], 0, N * 4, c->stream));
@@ -637,10 +664,17 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         TRY(dalloc(c, &c->coef, nb));
         stage.emplace_back(std::move(cf));
         TRY(upload(c->coef, stage.back().data(), 2 * nb * 4));
-        float *jblk = nullptr;
-        TRY(dalloc(c, &jblk, 3 * nb));
-        HIP_TRY(c, hipMemsetAsync(jblk, 0, 3 * nb * 4, c->stream));
-        for (int d = 0; d < 3; ++d) c->Jp[d] = jblk + d * nb;
+        if (blocks) {
+            float *jblk = nullptr;
+            TRY(dalloc(c, &jblk, 3 * nb));
+            HIP_TRY(c, hipMemsetAsync(jblk, 0, 3 * nb * 4, c->stream));
+            for (int d = 0; d < 3; ++d) c->Jp[d] = jblk + d * nb;
+        } else {
+            for (int d = 0; d < 3; ++d) {
+                TRY(dalloc(c, &c->Jp[d], nb));
+                HIP_TRY(c, hipMemsetAsync(c->Jp[d], 0, nb * 4, c->stream));
+            }
+        }
     }
 
     // CPML tables and psi slabs
@@ -667,14 +701,23 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         P.cH = dtab + 4 * n;
         P.kH = dtab + 5 * n;
         const size_t slab = (size_t)2 * g.npml * (N / (size_t)n);
-        float *pe = nullptr, *ph = nullptr;
-        TRY(dalloc(c, &pe, 2 * slab));
-        TRY(dalloc(c, &ph, 2 * slab));
-        HIP_TRY(c, hipMemsetAsync(pe, 0, 2 * slab * 4, c->stream));
-        HIP_TRY(c, hipMemsetAsync(ph, 0, 2 * slab * 4, c->stream));
-        for (int q = 0; q < 2; ++q) {
-            P.psiE[q] = pe + q * slab;
-            P.psiH[q] = ph + q * slab;
+        if (blocks) {
+            float *pe = nullptr, *ph = nullptr;
+            TRY(dalloc(c, &pe, 2 * slab));
+            TRY(dalloc(c, &ph, 2 * slab));
+            HIP_TRY(c, hipMemsetAsync(pe, 0, 2 * slab * 4, c->stream));
+            HIP_TRY(c, hipMemsetAsync(ph, 0, 2 * slab * 4, c->stream));
+            for (int q = 0; q < 2; ++q) {
+                P.psiE[q] = pe + q * slab;
+                P.psiH[q] = ph + q * slab;
+            }
+        } else {
+            for (int q = 0; q < 2; ++q) {
+                TRY(dalloc(c, &P.psiE[q], slab));
+                TRY(dalloc(c, &P.psiH[q], slab));
+                HIP_TRY(c, hipMemsetAsync(P.psiE[q], 0, slab * 4, c->stream));
+                HIP_TRY(c, hipMemsetAsync(P.psiH[q], 0, slab * 4, c->stream));
+            }
         }
     }
 
@@ -779,16 +822,25 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
                 HIP_TRY(c, hipMemsetAsync(c->Jq[d], 0, N * 8, c->stream));
             }
         }
-        float *jb = nullptr, *hv = nullptr;
-        if (c->deposit_mode != 2) {
-            TRY(dalloc(c, &jb, 3 * N));
-            HIP_TRY(c, hipMemsetAsync(jb, 0, 3 * N * 4, c->stream));
-        }
-        TRY(dalloc(c, &hv, 3 * N));
-        HIP_TRY(c, hipMemsetAsync(hv, 0, 3 * N * 4, c->stream));
-        for (int d = 0; d < 3; ++d) {
-            if (jb) c->Jb[d] = jb + d * N;
-            c->Havg[d] = hv + d * N;
+        if (blocks) {
+            float *jb = nullptr, *hv = nullptr;
+            TRY(dalloc(c, &jb, 2 * c->fs + N));
+            HIP_TRY(c, hipMemsetAsync(jb, 0, (2 * c->fs + N) * 4, c->stream));
+            TRY(dalloc(c, &hv, 2 * c->fs + N));
+            HIP_TRY(c, hipMemsetAsync(hv, 0, (2 * c->fs + N) * 4, c->stream));
+            for (int d = 0; d < 3; ++d) {
+                c->Jb[d] = jb + d * c->fs;
+                c->Havg[d] = hv + d * c->fs;
+            }
+        } else {
+            for (int d = 0; d < 3; ++d) {
+                if (c->deposit_mode != 2) {
+                    TRY(dalloc(c, &c->Jb[d], N));
+                    HIP_TRY(c, hipMemsetAsync(c->Jb[d], 0, N * 4, c->stream));
+                }
+                TRY(dalloc(c, &c->Havg[d], N));
+                HIP_TRY(c, hipMemsetAsync(c->Havg[d], 0, N * 4, c->stream));
+            }
         }
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         build_args(c);
@@ -804,12 +856,12 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
             HIP_TRY(c, hipGetLastError());
         }
     }
-    if (fused_eligible(g, o)) {
+    if (blocks) {
         // second blocks of the E-side state for the one-pass sweep
         c->fused = true;
         c->Eb[0] = c->E[0];
-        TRY(dalloc(c, &c->Eb[1], 3 * N));
-        HIP_TRY(c, hipMemsetAsync(c->Eb[1], 0, 3 * N * 4, c->stream));
+        TRY(dalloc(c, &c->Eb[1], 2 * c->fs + N));
+        HIP_TRY(c, hipMemsetAsync(c->Eb[1], 0, (2 * c->fs + N) * 4, c->stream));
         if (c->has_metal) {
             c->Jpb[0] = c->Jp[0];
             TRY(dalloc(c, &c->Jpb[1], 3 * c->nbox));
@@ -870,10 +922,16 @@ pic_status pic_query_sizes(const pic_grid *grid, int64_t nparticles, const pic_o
     // what pic_init allocates, in its order (dalloc of at least one element each)
     auto bytes = [](long long count, long long size) { return (count > 0 ? count : 1) * size; };
     long long total = 0;
-    int given = 0;
-    for (int d = 0; d < 3; ++d)
-        given += (o.bufs && o.bufs->E[d]) + (o.bufs && o.bufs->H[0][d]) + (o.bufs && o.bufs->H[1][d]);
-    total += (9 - given) * bytes(N, 4);                       // E, H ping-pong
+    const bool fused = fused_eligible(g, o);                 // field blocks (the sweep) or arrays
+    const long long FS = (long long)block_stride(o, (size_t)N);
+    for (int f = 0; f < 3; ++f) {                             // E, H ping-pong
+        const int gf = o.bufs ? (f == 0 ? (o.bufs->E[0] != nullptr) + (o.bufs->E[1] != nullptr) +
+                                              (o.bufs->E[2] != nullptr)
+                                        : (o.bufs->H[f - 1][0] != nullptr) + (o.bufs->H[f - 1][1] != nullptr) +
+                                              (o.bufs->H[f - 1][2] != nullptr))
+                              : 0;
+        total += gf == 0 && fused ? bytes(2 * FS + N, 4) : (3 - gf) * bytes(N, 4);
+    }
     total += bytes(1, 4) + bytes(16, 8) + bytes(1, 4) + bytes(1, sizeof(pic::DevState));
     for (int d = 0; d < 3; ++d) {                             // CPML tables and memories
         if (g.bc[d] != PIC_BC_CPML) continue;
@@ -892,13 +950,13 @@ pic_status pic_query_sizes(const pic_grid *grid, int64_t nparticles, const pic_o
         total += 3 * bytes(N + 1, 4) + bytes(6, 4);           // cell counts, runs, run starts; box
         total += bytes(6 * ((np + pic::PBLOCK - 1) / pic::PBLOCK), 4);
         total += bytes(pic::scan_tmp_size(N + 1), 4);
-        total += 3 * bytes(N, o.deposit_mode == 2 ? 8 : 4);   // J_b (fixed point: 64-bit)
-        total += 3 * bytes(N, 4);                             // time-centred H
+        const long long fblk = fused ? bytes(2 * FS + N, 4) : 3 * bytes(N, 4);
+        total += o.deposit_mode == 2 ? 3 * bytes(N, 8) : fblk;  // J_b (fixed point: 64-bit)
+        total += fblk;                                          // time-centred H
         if (o.diag) total += 2 * bytes((n[0] + 1) * (n[1] + 1) * (n[2] + 1), 8);
     }
-    const bool fused = fused_eligible(g, o);
     if (fused) {                                              // the sweep's second E-side blocks
-        total += bytes(3 * N, 4);
+        total += bytes(2 * FS + N, 4);
         for (int d = 0; d < 3; ++d)
             if (g.bc[d] == PIC_BC_CPML) total += bytes(2 * 2LL * g.npml * (N / n[d]), 4);
     }

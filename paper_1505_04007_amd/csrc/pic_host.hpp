@@ -99,6 +99,7 @@ struct pic_ctx {
     // memories) in two blocks each, ecur the one holding the current values;
     // every pic_step call ends with ecur = 0, the blocks pic_init set up
     bool fused = false;
+    size_t fs = 0;                              // component stride of the field blocks (floats)
     float *Eb[2] = {nullptr, nullptr};          // [3N]
     float *Jpb[2] = {nullptr, nullptr};         // [3 nbox]
     float *psiEb[3][2] = {};                    // per CPML axis [2 slab]

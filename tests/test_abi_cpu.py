@@ -190,6 +190,10 @@ def test_query_sizes_without_a_device():
     bc = (native.BC_CPML, native.BC_PERIODIC, native.BC_PEC)
     q = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=0, nprobe=3, nfreq=16)
     N = 40 * 24 * 30
+    # with the sweep, a field block the library allocates holds its three
+    # components N + PAD floats apart (caller fields keep their own spacing)
+    PAD = 262208
+    blk = 4 * (3 * N + 2 * PAD)
     assert q["field_elems"] == N and q["field_bytes"] == 4 * N
     assert q["bytes_per_metal_box_cell"] == 20
     assert q["device_bytes"] >= 9 * 4 * N
@@ -198,11 +202,12 @@ def test_query_sizes_without_a_device():
     withp = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=1000, nprobe=3, nfreq=16)
     assert withp["device_bytes"] - q["device_bytes"] >= 1000 * 2 * 7 * 4 + 6 * 4 * N
     fixed = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=1000, nprobe=3, nfreq=16, deposit_mode=2)
-    assert fixed["device_bytes"] - withp["device_bytes"] == 3 * 4 * N  # 64-bit bunch current, no sweep
-    # the one-pass sweep: a second E block, and per CPML axis a second block
-    # of the E-side memories (x: 2 * 2 * npml * ny * nz cells)
+    assert fixed["device_bytes"] - withp["device_bytes"] == 3 * 4 * N  # 64-bit bunch current
+    # the one-pass sweep: E, H[0], H[1], J_b and the time-centred H as padded
+    # blocks, a second E block, and per CPML axis a second block of the
+    # E-side memories (x: 2 * 2 * npml * ny * nz cells)
     sw = native.query_sizes(40, 24, 30, bc=bc, npml=4, nparticles=1000, nprobe=3, nfreq=16, field_sweep=1)
-    assert sw["device_bytes"] - withp["device_bytes"] == 3 * 4 * N + 2 * 2 * 4 * (N // 40) * 4
+    assert sw["device_bytes"] - withp["device_bytes"] == 5 * 8 * PAD + blk + 2 * 2 * 4 * (N // 40) * 4
     assert sw["bytes_per_metal_box_cell"] == 32
     wide = native.query_sizes(1025, 2, 2, nprobe=0, nfreq=0, field_sweep=1)  # x wider than a workgroup: no sweep
     assert wide["bytes_per_metal_box_cell"] == 20

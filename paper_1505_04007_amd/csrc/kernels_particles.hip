@@ -480,7 +480,8 @@ __device__ __forceinline__ void union_flush(float *J, const float *plus, const f
 // lane that does not deposit; knext: the key of lane + 1 (-1 past lane 63);
 // last: the lane ends its run.
 __device__ __forceinline__ void deposit_union(const PartArgs &a, float *val, int lane, int key, int knext,
-                                              bool last, int bxmin, int by, int bz, float *plus, float *minus)
+                                              bool last, int bxmin, int by, int bz, float *plus, float *minus,
+                                              bool ycross, bool zcross)
 {
     // one wavefront per workgroup: its LDS operations execute in program
     // order, and the wave barriers keep the compiler from moving the tiles'
@@ -490,8 +491,16 @@ __device__ __forceinline__ void deposit_union(const PartArgs &a, float *val, int
         reinterpret_cast<float4 *>(plus)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
         reinterpret_cast<float4 *>(minus)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    // a slot at node offset 2 along y (z) is exactly 0 for a move that stays
+    // in one y (z) cell: when no lane crosses, its prefix sums are 0 as well
 #pragma unroll
-    for (int s = 0; s < 54; ++s) val[s] = wave_prefix(val[s]);
+    for (int s = 0; s < 54; ++s) {
+        int comp, oi, oj, ok;
+        slot_geom(s, comp, oi, oj, ok);
+        const bool y2 = comp != 1 && oj == 2, z2 = comp != 2 && ok == 2;
+        if ((y2 && !ycross) || (z2 && !zcross)) continue;
+        val[s] = wave_prefix(val[s]);
+    }
     __builtin_amdgcn_wave_barrier();
     if (last && key >= 0) union_store(plus, key, val);
     if (last && knext >= 0) union_store(minus, knext, val);
@@ -527,6 +536,7 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
     // wavefront sum, and 0 x (uninitialised register) could be NaN
     Dep d = {};
     int base[3] = {0, 0, 0};
+    bool ycross = false, zcross = false;  // the move leaves its y (z) cell
     if (p < a.n) {
         const float x = X[p], y = Y[p], z = Z[p];
         if (live_pos(x, y, z, a.nx, a.ny, a.nz)) {
@@ -586,6 +596,8 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                 base[0] = min((int)floorf(x), (int)floorf(x1));
                 base[1] = min((int)floorf(y), (int)floorf(y1));
                 base[2] = min((int)floorf(z), (int)floorf(z1));
+                ycross = (int)floorf(y) != (int)floorf(y1);
+                zcross = (int)floorf(z) != (int)floorf(z1);
                 shapes(x, x1, base[0], S0[0], dS[0]);
                 shapes(y, y1, base[1], S0[1], dS[1]);
                 shapes(z, z1, base[2], S0[2], dS[2]);
@@ -634,7 +646,8 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                 const unsigned keys = wave_or_dpp(last && key >= 0 ? 1u << key : 0u);
                 if (__popc(keys) == __popcll(__ballot(last && key >= 0))) {
                     deposit_union(a, val, lane, key, knext, last, bxmin, by0, bz0, (float *)tplus4,
-                                  (float *)tminus4);
+                                  (float *)tminus4, __ballot(dep && ycross) != 0ull,
+                                  __ballot(dep && zcross) != 0ull);
                     rem = 0;
                 }
             }

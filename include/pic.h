@@ -132,7 +132,10 @@ typedef struct {
     const double *init_H[3];  /* optional H at t=-dt/2, compact Yee layout, A/m (NULL = zero);
                                  normal entries on PEC/CPML walls are taken as 0 */
     int32_t diag;             /* 1: keep the FP64 charge grid needed by the Gauss check */
-    int32_t timing;           /* 1: time every kernel launch with HIP events */
+    int32_t timing;           /* 1: time every kernel launch with HIP events; k > 1: only
+                                 the launches of the steps whose number (pic_stats steps
+                                 when the step starts) is a multiple of k, and every sort
+                                 (a sample with 1/k of the events' cost to the step) */
     int32_t deposit_mode;     /* 0: wavefront-reduced deposit (default), 1: per-lane atomics,
                                  2: wavefront-reduced into a 64-bit fixed-point current
                                  (each particle's edge currents rounded to 2^-24 of the
@@ -344,12 +347,14 @@ pic_status pic_diag(pic_ctx *ctx, pic_diag_out *out);
 pic_status pic_stats(pic_ctx *ctx, pic_stats_out *out);
 
 /*
- * Per-kernel device time (opts.timing = 1), measured with HIP events on the
+ * Per-kernel device time (opts.timing >= 1), measured with HIP events on the
  * context's stream.  names: kernel families in order
  *   0 h_update, 1 push_deposit, 2 e_update, 3 probe, 4 sort,
  *   5 field_sweep (the one-pass E + H update, with its clear of the bunch current).
- * ms_total[6], launches[6] receive the accumulated milliseconds and launch
- * counts since init or the last reset; reset = 1 clears them afterwards.
+ * ms_total[6], launches[6] receive the accumulated milliseconds and counts
+ * of the timed launches since init or the last reset (with timing = k > 1,
+ * those of the sampled steps and every sort); reset = 1 clears them
+ * afterwards.
  * The context holds two HIP events per timed launch until a reset: in a
  * long timed run, call with reset = 1 from time to time.
  */

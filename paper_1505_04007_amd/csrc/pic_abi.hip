@@ -169,13 +169,15 @@ void build_args(pic_ctx *c)
     pr.st = c->dstate;
 }
 
-// Launch timing (opts.timing): a pair of events around each launch.  A pair
-// that cannot be created is skipped (that launch goes untimed) rather than
-// recorded with invalid handles.
+// Launch timing (opts.timing): a pair of events around each launch of the
+// sampled steps (every step, or every timing_every-th) and around every sort.
+// A pair that cannot be created is skipped (that launch goes untimed) rather
+// than recorded with invalid handles.
 void tstart(pic_ctx *c, int fam)
 {
     c->timed_now = false;
     if (!c->timing) return;
+    if (fam != 4 && c->timing_every > 1 && c->step % c->timing_every != 0) return;
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess) {
         (void)hipGetLastError();
@@ -499,7 +501,9 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
     bind_static_scratch(c);
     c->sort_every = o.sort_every > 0 ? o.sort_every : 0;
     c->check_every = o.check_every > 0 ? o.check_every : 0;
+    if (o.timing < 0) return fail(c, PIC_EINVAL, "timing = %d must be >= 0", o.timing);
     c->timing = o.timing != 0;
+    c->timing_every = o.timing > 1 ? o.timing : 1;
     c->diag = o.diag != 0;
     if (o.deposit_mode < 0 || o.deposit_mode > 2)
         return fail(c, PIC_EINVAL, "deposit_mode = %d is not 0, 1 or 2", o.deposit_mode);

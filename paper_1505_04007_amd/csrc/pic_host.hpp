@@ -93,6 +93,7 @@ struct pic_ctx {
     long long since_sort = 0;
 
     bool timing = false;
+    int timing_every = 1;  // time the launches of every this many steps (and every sort)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[pich::kFamilies];
 
     // one-pass field sweep: the E-side state (E, J_pol, E-side CPML

@@ -240,7 +240,7 @@ class Simulation:
                 self._keep.append(a)
                 o.init_H[d] = _p(a)
         o.diag = int(bool(diag))
-        o.timing = int(bool(timing))
+        o.timing = int(timing)
         o.deposit_mode = int(deposit_mode)
         o.field_sweep = int(field_sweep)
         if device_fields:

@@ -100,7 +100,7 @@ def _init(**over):
     w = pi.slab_tiny(with_bunch=False)
     n = [w.nx, w.ny, w.nz]
     args = dict(n=n, bc=[0, 0, 0], npml=0, dx=w.dx, dt=w.dt, wp=w.wp_map, g=w.gamma_map, parts=None,
-                pml=(3.0, 1.0, 1.0, 0.0))
+                pml=(3.0, 1.0, 1.0, 0.0), opts={})
     args.update(over)
     g = native.PicGrid(*args["n"], (ctypes.c_int32 * 3)(*args["bc"]), args["npml"], *args["pml"])
     wp = native.to_compact(args["wp"])
@@ -114,9 +114,14 @@ def _init(**over):
         keep += arrs
         pp = native.PicParticles(len(arrs[0]), *[a.ctypes.data_as(native._dp) for a in arrs],
                                  *parts[6:])
+    o = None
+    if args["opts"]:
+        o = native.PicOpts()
+        for k, v in args["opts"].items():
+            setattr(o, k, v)
     st = lib.pic_init(ctypes.byref(h), ctypes.byref(g), args["dx"], args["dt"],
                       wp.ctypes.data_as(native._dp), gm.ctypes.data_as(native._dp),
-                      ctypes.byref(pp) if pp is not None else None, None)
+                      ctypes.byref(pp) if pp is not None else None, ctypes.byref(o) if o is not None else None)
     msg = lib.pic_last_error(None).decode()
     if h.value:
         lib.pic_destroy(h)
@@ -132,6 +137,9 @@ def _init(**over):
     (dict(dx=-1.0), "positive"),
     (dict(dt=1e-15), "dt/dx"),
     (dict(bc=[2, 2, 2], npml=4, pml=(3.0, 1.0, 0.5, 0.0)), "CPML"),
+    (dict(opts={"timing": -1}), "timing"),
+    (dict(opts={"deposit_mode": 3}), "deposit_mode"),
+    (dict(opts={"field_sweep": 2}), "field_sweep"),
 ])
 def test_init_rejects_invalid_problem(over, frag):
     st, msg = _init(**over)

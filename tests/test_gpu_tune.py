@@ -108,3 +108,26 @@ def test_tune_rejects_bad_arguments():
         with pytest.raises(native.PicError) as ei:
             s.tune(reps=reps, force=force)
         assert ei.value.status == native.PIC_EINVAL
+
+
+def test_sampled_timing_counts_the_sampled_steps_and_every_sort():
+    """timing = 3 from step 0 over 30 steps with a sort every 5: the launches
+    of steps 0, 3, ..., 27 (10 each) and all 6 sorts (pic_init's and those
+    before steps 5, 10, ..., 25); timing = 1 every launch.
+    Results are those of an untimed run."""
+    import dataclasses
+    w = dataclasses.replace(pi.slab_tiny(), sort_every=5)
+    out = {}
+    for t in (0, 1, 3):
+        sim = native.from_workload(w, timing=t)
+        sim.step(30)
+        out[t] = (sim.timing(), sim.fields(native.FIELD_E))
+        sim.close()
+    per_step = ("h_update", "push_deposit", "e_update", "probe")
+    for fam in per_step:
+        assert out[1][0][fam][1] == 30 and out[3][0][fam][1] == 10, fam
+        assert out[3][0][fam][0] > 0, fam
+        assert out[0][0][fam] == (0.0, 0), fam
+    assert out[1][0]["sort"][1] == 6 and out[3][0]["sort"][1] == 6
+    rel = np.linalg.norm(out[3][1] - out[0][1]) / np.linalg.norm(out[0][1])
+    assert rel <= 1e-5  # the FP32 deposit's atomics order aside, the same run

@@ -538,17 +538,24 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
     int base[3] = {0, 0, 0};
     bool ycross = false, zcross = false;  // the move leaves its y (z) cell
     if (p < a.n) {
+        // The gather and Boris run for every lane, with no branch on liveness
+        // before them, so that all six particle loads go out together (a
+        // branch lets the compiler sink loads below it, each sunk group one
+        // more round trip to memory).  A lost particle gathers at the box
+        // corner, a valid position, and nothing of it is written.
         const float x = X[p], y = Y[p], z = Z[p];
-        if (live_pos(x, y, z, a.nx, a.ny, a.nz)) {
-            float u0 = UX[p], u1 = UY[p], u2 = UZ[p];
+        float u0 = UX[p], u1 = UY[p], u2 = UZ[p];
+        const bool live = live_pos(x, y, z, a.nx, a.ny, a.nz);
+        const float xg = live ? x : 0.f, yg = live ? y : 0.f, zg = live ? z : 0.f;
+        {
             Axis2 AY, AZ;
-            axis_corners(y, a.ny, a.per[1], a.nx, AY);
-            axis_corners(z, a.nz, a.per[2], a.nx * a.ny, AZ);
+            axis_corners(yg, a.ny, a.per[1], a.nx, AY);
+            axis_corners(zg, a.nz, a.per[2], a.nx * a.ny, AZ);
             // E^n and Ht^n = (Ht^{n-1/2} + Ht^{n+1/2})/2 at x^n
             float e0, e1, e2, h0, h1, h2;
             if (PX) {
                 Axis2 AX;
-                axis_corners(x, a.nx, a.per[0], 1, AX);
+                axis_corners(xg, a.nx, a.per[0], 1, AX);
                 e0 = gather_scalar<1, 0, 0>(a.E[0], AX, AY, AZ);
                 e1 = gather_scalar<0, 1, 0>(a.E[1], AX, AY, AZ);
                 e2 = gather_scalar<0, 0, 1>(a.E[2], AX, AY, AZ);
@@ -557,7 +564,7 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                 h2 = gather_scalar<1, 1, 0>(a.B[2], AX, AY, AZ);
             } else {
                 XPair XP;
-                x_pairs(x, a.nx, XP);
+                x_pairs(xg, a.nx, XP);
                 e0 = gather_pair<1, 0, 0>(a.E[0], XP, AY, AZ);
                 e1 = gather_pair<0, 1, 0>(a.E[1], XP, AY, AZ);
                 e2 = gather_pair<0, 0, 1>(a.E[2], XP, AY, AZ);
@@ -578,6 +585,8 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
             u0 = m0 + (p1 * s2 - p2 * s1) + ah * e0;
             u1 = m1 + (p2 * s0 - p0 * s2) + ah * e1;
             u2 = m2 + (p0 * s1 - p1 * s0) + ah * e2;
+        }
+        if (live) {
             const float g = rsqrtf(1.f + u0 * u0 + u1 * u1 + u2 * u2);
             float x1 = x + a.S * u0 * g, y1 = y + a.S * u1 * g, z1 = z + a.S * u2 * g;
             // leaving through a wall, or a non-finite move, deactivates the particle

@@ -634,7 +634,9 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
     }
     const unsigned long long live = __ballot(dep);
     // per-wavefront push counter (one slot per wavefront of the launch)
-    if (lane == 0 && live) G(a.pushes)[p >> 6] += (unsigned long long)__popcll(live);
+    // (an atomic whose result is unused: the wavefront does not wait for the
+    // counter's old value as a load-add-store would)
+    if (lane == 0 && live) gatomic_add(G(a.pushes) + (p >> 6), (unsigned long long)__popcll(live));
     unsigned long long rem = live;
     if (MODE == 0 && !FIX && live) {
         // one grid row of windows spanning at least two x bases: the row-union tiles
@@ -748,7 +750,8 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit(PartArgs a)
 // Many simulations in one launch: workgroup b is push block own[b] & 0xffffff
 // of simulation own[b] >> 24 (a table the host builds).
 template <int MODE, int PX>
-__global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit_batch(const PartArgs *args, const int *own)
+__global__ __launch_bounds__(PUSH_BLOCK) void k_push_deposit_batch(const PartArgs *__restrict__ args,
+                                                                   const int *__restrict__ own)
 {
     const int o = own[blockIdx.x];
     push_body<MODE, PX, 0>(args[o >> 24], o & 0xffffff);

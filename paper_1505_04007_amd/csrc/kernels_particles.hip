@@ -818,9 +818,17 @@ __device__ __forceinline__ int wave_minmax(int v)
 
 // Cell key of a particle position (the lost-particle bucket ncell when it is
 // not live).
+// live_pos evaluated without short-circuit: every coordinate is read before
+// the test, so the compiler cannot sink the loads of y and z below a branch
+// on x (each sunk group would be one more round trip to memory).
+__device__ __forceinline__ bool live_all(float x, float y, float z, int nx, int ny, int nz)
+{
+    return (x >= 0.f) & (x < (float)nx) & (y >= 0.f) & (y < (float)ny) & (z >= 0.f) & (z < (float)nz);
+}
+
 __device__ __forceinline__ int cell_key(float x, float y, float z, int nx, int ny, int nz)
 {
-    if (!live_pos(x, y, z, nx, ny, nz)) return nx * ny * nz;
+    if (!live_all(x, y, z, nx, ny, nz)) return nx * ny * nz;
     return min((int)x, nx - 1) + nx * (min((int)y, ny - 1) + ny * min((int)z, nz - 1));
 }
 
@@ -846,9 +854,17 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
     int key = a.ncell;
     int cell[3] = {INT_MAX, INT_MAX, INT_MAX};
     bool in = false;
+    // lane 0 also needs the cell of particle p - 1 (the run test below):
+    // its position is loaded here, with the lane's own
+    float xq = -1.f, yq = -1.f, zq = -1.f;
+    if (lane == 0 && p > 0 && p <= a.n) {
+        xq = a.P[pc][0][p - 1];
+        yq = a.P[pc][1][p - 1];
+        zq = a.P[pc][2][p - 1];
+    }
     if (p < a.n) {
         const float x = a.P[pc][0][p], y = a.P[pc][1][p], z = a.P[pc][2][p];
-        if (live_pos(x, y, z, a.nx, a.ny, a.nz)) {
+        if (live_all(x, y, z, a.nx, a.ny, a.nz)) {
             cell[0] = min((int)x, a.nx - 1);
             cell[1] = min((int)y, a.ny - 1);
             cell[2] = min((int)z, a.nz - 1);
@@ -879,8 +895,7 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
     }
     // key of particle p - 1: the lane below, or for lane 0 from its position
     int kprev = __builtin_amdgcn_update_dpp(-1, key, 0x138, 0xf, 0xf, false);  // wave_shr:1
-    if (lane == 0 && p > 0 && p <= a.n)
-        kprev = cell_key(a.P[pc][0][p - 1], a.P[pc][1][p - 1], a.P[pc][2][p - 1], a.nx, a.ny, a.nz);
+    if (lane == 0 && p > 0 && p <= a.n) kprev = cell_key(xq, yq, zq, a.nx, a.ny, a.nz);
     if (p < a.n && (p == 0 || kprev != key)) {
         atomicAdd(&a.runs[key], 1);
         a.first[key] = p;
@@ -1042,10 +1057,21 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_scatter(SortArgs a)
     const int p = blockIdx.x * PBLOCK + threadIdx.x;
     if (p >= a.n) return;
     const int pc = a.st->pcur;
+    // every load first, in two rounds (the particle, its key and rank; then
+    // the key's count and run), then the stores: the stores to the other
+    // buffer set may alias the loads as far as the compiler knows, so a load
+    // after a store would wait for it
+    float v[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = a.P[pc][c][p];
+    const int id = a.id[pc][p];
     const int k = a.key[p];
-    const int dst = a.counts[k] + (a.runs[k] == 1 ? p - a.first[k] : a.rank[p]);
-    for (int c = 0; c < 6; ++c) a.P[pc ^ 1][c][dst] = a.P[pc][c][p];
-    a.id[pc ^ 1][dst] = a.id[pc][p];
+    const int rk = a.rank[p];
+    const int cnt = a.counts[k], runs = a.runs[k], f = a.first[k];
+    const int dst = cnt + (runs == 1 ? p - f : rk);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a.P[pc ^ 1][c][dst] = v[c];
+    a.id[pc ^ 1][dst] = id;
 }
 
 // After the scatter: the sorted set becomes current and the sort clock restarts.

@@ -41,9 +41,11 @@ constexpr int TILE_FX[N_TILE_SHAPES] = {64, 64, 128, 256, 32, 64, 128, 32, 64, 6
 constexpr int TILE_FY[N_TILE_SHAPES] = {4, 2, 2, 1, 8, 8, 4, 4, 4, 2, 2, 1, 8, 8, 4, 4};
 constexpr int TILE_ZO[N_TILE_SHAPES] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1};
 // A batched field launch gives each workgroup this many consecutive tiles of
-// one member: the member lookup (work-unit table, argument block, device
-// state: three dependent loads) is then paid once per four tiles.
-constexpr int BATCH_TILES = 4;
+// one member.  One: a workgroup's tiles run one after another (the next
+// tile's loads wait for the last one's stores, which may alias them as far
+// as the compiler knows), which costs more than the member lookup (work-unit
+// table, argument block, device state) it would share.
+constexpr int BATCH_TILES = 1;
 
 struct DevState {
     int parity;      // H[parity] holds H^{n-1/2} at the start of step n

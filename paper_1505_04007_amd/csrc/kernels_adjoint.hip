@@ -58,23 +58,49 @@ __device__ __forceinline__ bool e_masked(const AdjArgs &a, int i, int j, int k)
     return C == 0 ? (wy || wz) : C == 1 ? (wx || wz) : (wx || wy);
 }
 
+// A weight in two halves, so that a thread issues every load it needs before
+// it uses any (a slab value loaded and used weight by weight would be one
+// round trip to memory each): load() reads the weight's CPML value where the
+// weight is one, use() gives the weight.
+struct Weight {
+    bool zero, slab;
+    float v;
+};
+
 // Adjoint weight of the H difference along AX taken by the update of E
-// component C (sign SGN in that update, CPML memory slot Q) at edge (i,j,k).
-template <int C, int AX, int Q, int SGN>
-__device__ __forceinline__ float e_weight(const AdjArgs &a, float ebar, int i, int j, int k)
+// component C (sign SGN in that update, CPML memory slot Q) at edge (i,j,k):
+// 0 where the edge is never written, the stored slab weight inside the slab,
+// else +-S times the edge's adjoint value.
+template <int C, int AX, int Q>
+__device__ __forceinline__ Weight e_weight_load(const AdjArgs &a, int i, int j, int k)
 {
-    if (e_masked<C>(a, i, j, k)) return 0.f;
-    if (in_slab<AX>(a, i, j, k)) return a.DE[AX][Q][slab_sid<AX>(a, i, j, k)];
-    return (SGN > 0 ? a.S : -a.S) * ebar;
+    Weight w;
+    w.zero = e_masked<C>(a, i, j, k);
+    w.slab = !w.zero && in_slab<AX>(a, i, j, k);
+    w.v = 0.f;
+    if (w.slab) w.v = a.DE[AX][Q][slab_sid<AX>(a, i, j, k)];
+    return w;
 }
 
 // Adjoint weight of the E difference along AX taken by an H update (sign SGN,
 // slot Q) at face (i,j,k).
-template <int AX, int Q, int SGN>
-__device__ __forceinline__ float h_weight(const AdjArgs &a, float hbar, int i, int j, int k)
+template <int AX, int Q>
+__device__ __forceinline__ Weight h_weight_load(const AdjArgs &a, int i, int j, int k)
 {
-    if (in_slab<AX>(a, i, j, k)) return a.DH[AX][Q][slab_sid<AX>(a, i, j, k)];
-    return (SGN > 0 ? a.S : -a.S) * hbar;
+    Weight w;
+    w.zero = false;
+    w.slab = in_slab<AX>(a, i, j, k);
+    w.v = 0.f;
+    if (w.slab) w.v = a.DH[AX][Q][slab_sid<AX>(a, i, j, k)];
+    return w;
+}
+
+template <int SGN>
+__device__ __forceinline__ float weight(const AdjArgs &a, const Weight &w, float bar)
+{
+    if (w.zero) return 0.f;
+    if (w.slab) return w.v;
+    return (SGN > 0 ? a.S : -a.S) * bar;
 }
 
 // Transpose of  psi' = b psi + c d,  d_eff = d / kappa + psi'  given the
@@ -130,20 +156,28 @@ __global__ __launch_bounds__(FX *FY) void k_adj_face(AdjArgs a)
     const float eyx = Ey[id + ox], ezx = Ez[id + ox];
     const float exy = Ex[id + oy], ezy = Ez[id + oy];
     const float exz = Ex[id + oz], eyz = Ey[id + oz];
+    const float hx0 = a.Ha[0][id], hy0 = a.Ha[1][id], hz0 = a.Ha[2][id];
+    // (ip, jp, kp are valid cells whether or not the neighbour takes part)
+    const Weight wx0 = e_weight_load<1, 2, 1>(a, i, j, k), wx1 = e_weight_load<2, 1, 1>(a, i, j, k);
+    const Weight wx2 = e_weight_load<1, 2, 1>(a, i, j, kp), wx3 = e_weight_load<2, 1, 1>(a, i, jp, k);
+    const Weight wy0 = e_weight_load<0, 2, 0>(a, i, j, k), wy1 = e_weight_load<2, 0, 1>(a, i, j, k);
+    const Weight wy2 = e_weight_load<0, 2, 0>(a, i, j, kp), wy3 = e_weight_load<2, 0, 1>(a, ip, j, k);
+    const Weight wz0 = e_weight_load<0, 1, 0>(a, i, j, k), wz1 = e_weight_load<1, 0, 0>(a, i, j, k);
+    const Weight wz2 = e_weight_load<0, 1, 0>(a, i, jp, k), wz3 = e_weight_load<1, 0, 0>(a, ip, j, k);
 
-    float gx = e_weight<1, 2, 1, +1>(a, ey, i, j, k) + e_weight<2, 1, 1, -1>(a, ez, i, j, k);
-    if (okz) gx -= e_weight<1, 2, 1, +1>(a, eyz, i, j, kp);
-    if (oky) gx -= e_weight<2, 1, 1, -1>(a, ezy, i, jp, k);
-    float gy = e_weight<0, 2, 0, -1>(a, ex, i, j, k) + e_weight<2, 0, 1, +1>(a, ez, i, j, k);
-    if (okz) gy -= e_weight<0, 2, 0, -1>(a, exz, i, j, kp);
-    if (okx) gy -= e_weight<2, 0, 1, +1>(a, ezx, ip, j, k);
-    float gz = e_weight<0, 1, 0, +1>(a, ex, i, j, k) + e_weight<1, 0, 0, -1>(a, ey, i, j, k);
-    if (oky) gz -= e_weight<0, 1, 0, +1>(a, exy, i, jp, k);
-    if (okx) gz -= e_weight<1, 0, 0, -1>(a, eyx, ip, j, k);
+    float gx = weight<+1>(a, wx0, ey) + weight<-1>(a, wx1, ez);
+    if (okz) gx -= weight<+1>(a, wx2, eyz);
+    if (oky) gx -= weight<-1>(a, wx3, ezy);
+    float gy = weight<-1>(a, wy0, ex) + weight<+1>(a, wy1, ez);
+    if (okz) gy -= weight<-1>(a, wy2, exz);
+    if (okx) gy -= weight<+1>(a, wy3, ezx);
+    float gz = weight<+1>(a, wz0, ex) + weight<-1>(a, wz1, ey);
+    if (oky) gz -= weight<+1>(a, wz2, exy);
+    if (okx) gz -= weight<-1>(a, wz3, eyx);
 
-    const float hx = a.Ha[0][id] + gx;
-    const float hy = a.Ha[1][id] + gy;
-    const float hz = a.Ha[2][id] + gz;
+    const float hx = hx0 + gx;
+    const float hy = hy0 + gy;
+    const float hz = hz0 + gz;
     a.Ha[0][id] = hx;
     a.Ha[1][id] = hy;
     a.Ha[2][id] = hz;
@@ -190,16 +224,23 @@ __global__ __launch_bounds__(FX *FY) void k_adj_edge(AdjArgs a)
         const float hyx = Hy[id + ox], hzx = Hz[id + ox];
         const float hxy = Hx[id + oy], hzy = Hz[id + oy];
         const float hxz = Hx[id + oz], hyz = Hy[id + oz];
+        // (im, jm, km are valid cells whether or not the neighbour takes part)
+        const Weight vx0 = h_weight_load<2, 1>(a, i, j, k), vx1 = h_weight_load<1, 1>(a, i, j, k);
+        const Weight vx2 = h_weight_load<2, 1>(a, i, j, km), vx3 = h_weight_load<1, 1>(a, i, jm, k);
+        const Weight vy0 = h_weight_load<2, 0>(a, i, j, k), vy1 = h_weight_load<0, 1>(a, i, j, k);
+        const Weight vy2 = h_weight_load<2, 0>(a, i, j, km), vy3 = h_weight_load<0, 1>(a, im, j, k);
+        const Weight vz0 = h_weight_load<1, 0>(a, i, j, k), vz1 = h_weight_load<0, 0>(a, i, j, k);
+        const Weight vz2 = h_weight_load<1, 0>(a, i, jm, k), vz3 = h_weight_load<0, 0>(a, im, j, k);
         // each face m reads E(m + e_a) with + and E(m) with -
-        ex -= h_weight<2, 1, -1>(a, hy, i, j, k) + h_weight<1, 1, +1>(a, hz, i, j, k);
-        if (okz) ex += h_weight<2, 1, -1>(a, hyz, i, j, km);
-        if (oky) ex += h_weight<1, 1, +1>(a, hzy, i, jm, k);
-        ey -= h_weight<2, 0, +1>(a, hx, i, j, k) + h_weight<0, 1, -1>(a, hz, i, j, k);
-        if (okz) ey += h_weight<2, 0, +1>(a, hxz, i, j, km);
-        if (okx) ey += h_weight<0, 1, -1>(a, hzx, im, j, k);
-        ez -= h_weight<1, 0, -1>(a, hx, i, j, k) + h_weight<0, 0, +1>(a, hy, i, j, k);
-        if (oky) ez += h_weight<1, 0, -1>(a, hxy, i, jm, k);
-        if (okx) ez += h_weight<0, 0, +1>(a, hyx, im, j, k);
+        ex -= weight<-1>(a, vx0, hy) + weight<+1>(a, vx1, hz);
+        if (okz) ex += weight<-1>(a, vx2, hyz);
+        if (oky) ex += weight<+1>(a, vx3, hzy);
+        ey -= weight<+1>(a, vy0, hx) + weight<-1>(a, vy1, hz);
+        if (okz) ey += weight<+1>(a, vy2, hxz);
+        if (okx) ey += weight<-1>(a, vy3, hzx);
+        ez -= weight<-1>(a, vz0, hx) + weight<+1>(a, vz1, hy);
+        if (oky) ez += weight<-1>(a, vz2, hxy);
+        if (okx) ez += weight<+1>(a, vz3, hyx);
 
         if (i >= a.mlo[0] && i < a.mhi[0] && j >= a.mlo[1] && j < a.mhi[1] && k >= a.mlo[2] &&
             k < a.mhi[2]) {

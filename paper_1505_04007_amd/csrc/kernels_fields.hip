@@ -123,6 +123,9 @@ __device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, 
     const float hx = ld_once(H0 + id), hy = ld_once(H1 + id), hz = ld_once(H2 + id);
     SlabMem mx, my, mz;
     slab_all<0>(a, i, j, k, mx, my, mz);
+    // tested with the cell's loads: after the first store its box loads
+    // would be one more trip to memory
+    const bool avg = a.Havg[0] && in_particle_box(a, margin, i, j, k);
     eyx = okx ? eyx : 0.f;
     ezx = okx ? ezx : 0.f;
     exy = oky ? exy : 0.f;
@@ -151,7 +154,7 @@ __device__ __forceinline__ void h_cell(const FieldArgs &a, int par, int margin, 
     st_once(O0 + id, nhx);
     st_once(O1 + id, nhy);
     st_once(O2 + id, nhz);
-    if (a.Havg[0] && in_particle_box(a, margin, i, j, k)) {
+    if (avg) {
         // B^n of the push, (Ht^{n-1/2} + Ht^{n+1/2})/2, where particles can gather it
         G(a.Havg[0])[id] = 0.5f * (hx + nhx);
         G(a.Havg[1])[id] = 0.5f * (hy + nhy);

@@ -524,13 +524,15 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
 {
     const int p = blk * PUSH_BLOCK + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const int pc = G(a.st)->pcur;
-    const gp<float> __restrict__ X = G(a.P[pc][0]);
-    const gp<float> __restrict__ Y = G(a.P[pc][1]);
-    const gp<float> __restrict__ Z = G(a.P[pc][2]);
-    const gp<float> __restrict__ UX = G(a.P[pc][3]);
-    const gp<float> __restrict__ UY = G(a.P[pc][4]);
-    const gp<float> __restrict__ UZ = G(a.P[pc][5]);
+    // the current set's arrays straight from the device state (one scalar
+    // load after the state's address, not the set index and then its arrays)
+    const gp<const DevState> st = G(a.st);
+    const gp<float> __restrict__ X = G(st->P[0]);
+    const gp<float> __restrict__ Y = G(st->P[1]);
+    const gp<float> __restrict__ Z = G(st->P[2]);
+    const gp<float> __restrict__ UX = G(st->P[3]);
+    const gp<float> __restrict__ UY = G(st->P[4]);
+    const gp<float> __restrict__ UZ = G(st->P[5]);
     bool dep = false;
     // zeroed: a lane that does not deposit is silenced by a factor 0 in the
     // wavefront sum, and 0 x (uninitialised register) could be NaN
@@ -1075,11 +1077,13 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_scatter(SortArgs a)
 }
 
 // After the scatter: the sorted set becomes current and the sort clock restarts.
-__global__ void k_sort_done(DevState *st)
+__global__ void k_sort_done(SortArgs a)
 {
     if (threadIdx.x == 0) {
-        st->pcur ^= 1;
-        st->since_sort = 0;
+        const int pc = a.st->pcur ^ 1;
+        a.st->pcur = pc;
+        a.st->since_sort = 0;
+        for (int c = 0; c < 6; ++c) a.st->P[c] = a.P[pc][c];
     }
 }
 
@@ -1107,7 +1111,7 @@ void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s)
     if (a.n > 0) {
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(PBLOCK), 0, s, a);
     }
-    hipLaunchKernelGGL(k_sort_done, dim3(1), dim3(64), 0, s, a.st);
+    hipLaunchKernelGGL(k_sort_done, dim3(1), dim3(64), 0, s, a);
 }
 
 }  // namespace pic

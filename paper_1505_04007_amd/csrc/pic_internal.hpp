@@ -53,6 +53,7 @@ struct DevState {
     int pcur;        // particle buffer set in use
     int pad;
     long long step;  // steps taken
+    float *P[6];     // set pcur's arrays (x, y, z, ux, uy, uz), written with pcur by the sort
 };
 
 // CPML data of one axis.  Coefficients are per position along the axis:

@@ -298,7 +298,7 @@ template <int TXW, int TYW, int ZO>
 __global__ __launch_bounds__(TXW *TYW) void k_e_update(FieldArgs a)
 {
     int i, j, k;
-    if (!tile_cell<TXW, TYW, ZO>(a, xcd_tile(), i, j, k)) return;
+    if (!tile_cell<TXW, TYW, ZO>(a, xcd_tile_rev(), i, j, k)) return;
     const gp<const DevState> st = G(a.st);
     e_cell(a, st->parity, box_margin(st->since_sort, a.S), i, j, k);
 }
@@ -326,7 +326,7 @@ template <int TXW, int TYW, int ZO>
 __global__ __launch_bounds__(TXW *TYW) void k_e_update_batch(const FieldArgs *__restrict__ args,
                                                              const int *__restrict__ own)
 {
-    const int o = own[xcd_tile()];
+    const int o = own[xcd_tile_rev()];
     const FieldArgs &a = args[o >> 24];
     const gp<const DevState> st = G(a.st);
     const int parity = st->parity, margin = box_margin(st->since_sort, a.S);

@@ -264,6 +264,17 @@ __device__ __forceinline__ int xcd_tile()
     return (B % 8 == 0) ? (b % 8) * (B / 8) + b / 8 : b;
 }
 
+// xcd_tile() with each XCD walking its range from the end: a launch that
+// follows one in the forward order starts on the tiles the other wrote last,
+// which are still in the Infinity Cache.
+__device__ __forceinline__ int xcd_tile_rev()
+{
+    const int B = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, i = b >> 3, q = B >> 3, r = B & 7;
+    const int len = q + (x < r ? 1 : 0);
+    return x * q + min(x, r) + (len - 1 - i);
+}
+
 // Position of plane q inside the two absorbing slabs of an axis.
 __device__ __forceinline__ int slab_p(int q, int n, int np) { return q < np ? q : q - (n - 2 * np); }
 

@@ -544,9 +544,13 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
         // before them, so that all six particle loads go out together (a
         // branch lets the compiler sink loads below it, each sunk group one
         // more round trip to memory).  A lost particle gathers at the box
-        // corner, a valid position, and nothing of it is written.
-        const float x = X[p], y = Y[p], z = Z[p];
-        float u0 = UX[p], u1 = UY[p], u2 = UZ[p];
+        // corner, a valid position, and nothing of it is written.  The
+        // particle state streams with the non-temporal hint: it is touched
+        // once per step, and the fields around it should stay cached.
+        const float x = __builtin_nontemporal_load(X + p), y = __builtin_nontemporal_load(Y + p),
+                    z = __builtin_nontemporal_load(Z + p);
+        float u0 = __builtin_nontemporal_load(UX + p), u1 = __builtin_nontemporal_load(UY + p),
+              u2 = __builtin_nontemporal_load(UZ + p);
         const bool live = live_pos(x, y, z, a.nx, a.ny, a.nz);
         const float xg = live ? x : 0.f, yg = live ? y : 0.f, zg = live ? z : 0.f;
         {
@@ -596,11 +600,11 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                              (!a.per[0] && !(x1 >= 0.f && x1 < (float)a.nx)) ||
                              (!a.per[1] && !(y1 >= 0.f && y1 < (float)a.ny)) ||
                              (!a.per[2] && !(z1 >= 0.f && z1 < (float)a.nz));
-            UX[p] = u0;
-            UY[p] = u1;
-            UZ[p] = u2;
+            __builtin_nontemporal_store(u0, UX + p);
+            __builtin_nontemporal_store(u1, UY + p);
+            __builtin_nontemporal_store(u2, UZ + p);
             if (out) {
-                X[p] = -1.f;  // left the box: deactivated, last move not deposited
+                __builtin_nontemporal_store(-1.f, X + p);  // left the box: deactivated, last move not deposited
             } else {
                 // written out per axis: constant indices keep S0/dS in registers
                 float S0[3][3], dS[3][3];
@@ -617,9 +621,9 @@ __device__ __forceinline__ void push_body(const PartArgs &a, int blk)
                 if (a.per[0]) x1 = fold(x1, a.nx);
                 if (a.per[1]) y1 = fold(y1, a.ny);
                 if (a.per[2]) z1 = fold(z1, a.nz);
-                X[p] = x1;
-                Y[p] = y1;
-                Z[p] = z1;
+                __builtin_nontemporal_store(x1, X + p);
+                __builtin_nontemporal_store(y1, Y + p);
+                __builtin_nontemporal_store(z1, Z + p);
             }
         }
     }

@@ -115,8 +115,6 @@ void build_args(pic_ctx *c)
     pic::PartArgs &pa = c->pa;
     pa = pic::PartArgs{};
     pa.n = c->np;
-    for (int s2 = 0; s2 < 2; ++s2)
-        for (int q = 0; q < 6; ++q) pa.P[s2][q] = c->P[s2][q];
     pa.nx = c->n[0];
     pa.ny = c->n[1];
     pa.nz = c->n[2];

@@ -136,8 +136,7 @@ struct FusedArgs {
 };
 
 struct PartArgs {
-    int n;
-    float *P[2][6];  // x, y, z, ux, uy, uz for each buffer set
+    int n;  // particles; their arrays are the device state's P (the current buffer set)
     int nx, ny, nz;
     int per[3];
     const float *E[3];

@@ -974,25 +974,67 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *sm, int &total)
     return incl - v;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const int *in, long long n, int *tile_sums)
+// The keys a sort gives out: the cells of its live-cell box (the count
+// kernel's), in global key order, then the lost-particle bucket (key ncell).
+// Element e of that list.  The scans run over it alone: a key outside the box
+// has no particle, so its offset is never read, and the offsets inside are
+// those of a scan over every cell.
+struct KeyDomain {
+    int lo[3], w[3];
+    long long cells;  // box cells; the list has cells + 1 entries
+};
+
+__device__ __forceinline__ KeyDomain key_domain(const SortArgs &a)
+{
+    KeyDomain D;
+    D.cells = 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int lo = a.box[d], hi = a.box[3 + d];
+        D.lo[d] = lo;
+        D.w[d] = hi >= lo ? hi - lo + 1 : 0;
+        D.cells *= D.w[d];
+    }
+    return D;
+}
+
+__device__ __forceinline__ long long domain_key(const SortArgs &a, const KeyDomain &D, long long e)
+{
+    if (e >= D.cells) return a.ncell;
+    const long long r = e / D.w[0];
+    const int x = (int)(e - r * D.w[0]);
+    const long long z = r / D.w[1];
+    const int y = (int)(r - z * D.w[1]);
+    return (long long)(D.lo[0] + x) + (long long)a.nx * ((D.lo[1] + y) + (long long)a.ny * (D.lo[2] + (int)z));
+}
+
+// Workgroups of the scan launches: a fixed grid walking the list's tiles (the
+// list's length is known on the device only).
+constexpr int SCAN_BLOCKS = 1024;
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(SortArgs a, int *tile_sums)
 {
     __shared__ int sm[SCAN_THREADS];
-    const long long b0 = (long long)blockIdx.x * SCAN_TILE;
-    int s = 0;
-    for (int q = 0; q < SCAN_ITEMS; ++q) {
-        const long long idx = b0 + (long long)q * SCAN_THREADS + threadIdx.x;
-        if (idx < n) s += in[idx];
+    const KeyDomain D = key_domain(a);
+    const long long n = D.cells + 1;
+    for (long long b0 = (long long)blockIdx.x * SCAN_TILE; b0 < n; b0 += (long long)gridDim.x * SCAN_TILE) {
+        int s = 0;
+        for (int q = 0; q < SCAN_ITEMS; ++q) {
+            const long long e = b0 + (long long)q * SCAN_THREADS + threadIdx.x;
+            if (e < n) s += a.counts[domain_key(a, D, e)];
+        }
+        int total;
+        block_exclusive_scan(s, sm, total);
+        if (threadIdx.x == 0) tile_sums[b0 / SCAN_TILE] = total;
     }
-    int total;
-    block_exclusive_scan(s, sm, total);
-    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
 // One workgroup; each thread scans SCAN_ITEMS consecutive tile sums of a
 // chunk serially around one block scan of the thread totals.
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(int *tile_sums, int ntiles)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(SortArgs a, int *tile_sums)
 {
     __shared__ int sm[SCAN_THREADS];
+    const int ntiles = (int)((key_domain(a).cells + 1 + SCAN_TILE - 1) / SCAN_TILE);
     int carry = 0;
     for (int b0 = 0; b0 < ntiles; b0 += SCAN_TILE) {
         const int first = b0 + threadIdx.x * SCAN_ITEMS;
@@ -1014,47 +1056,44 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(int *tile_sums, int 
     }
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(int *data, long long n, const int *tile_sums)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(SortArgs a, const int *tile_sums)
 {
     __shared__ int sm[SCAN_THREADS];
-    // each thread owns SCAN_ITEMS consecutive elements of the tile, moved as
-    // 16-byte vectors where the whole group lies inside the array
-    static_assert(SCAN_ITEMS % 4 == 0, "vector groups of 4");
-    const long long b0 = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
-    const bool full = b0 + SCAN_ITEMS <= n;
-    int vals[SCAN_ITEMS];
-    if (full) {
+    const KeyDomain D = key_domain(a);
+    const long long n = D.cells + 1;
+    for (long long t0 = (long long)blockIdx.x * SCAN_TILE; t0 < n; t0 += (long long)gridDim.x * SCAN_TILE) {
+        // each thread owns SCAN_ITEMS consecutive entries of the tile
+        const long long b0 = t0 + (long long)threadIdx.x * SCAN_ITEMS;
+        long long g[SCAN_ITEMS];
+        int vals[SCAN_ITEMS];
 #pragma unroll
-        for (int q = 0; q < SCAN_ITEMS; q += 4) {
-            const int4 v = *reinterpret_cast<const int4 *>(data + b0 + q);
-            vals[q] = v.x;
-            vals[q + 1] = v.y;
-            vals[q + 2] = v.z;
-            vals[q + 3] = v.w;
+        for (int q = 0; q < SCAN_ITEMS; ++q) {
+            g[q] = b0 + q < n ? domain_key(a, D, b0 + q) : -1;
+            vals[q] = g[q] >= 0 ? a.counts[g[q]] : 0;
         }
-    } else {
+        int s = 0;
 #pragma unroll
-        for (int q = 0; q < SCAN_ITEMS; ++q) vals[q] = b0 + q < n ? data[b0 + q] : 0;
+        for (int q = 0; q < SCAN_ITEMS; ++q) s += vals[q];
+        int total;
+        int run = block_exclusive_scan(s, sm, total) + tile_sums[t0 / SCAN_TILE];
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS; ++q) {
+            if (g[q] >= 0) a.counts[g[q]] = run;
+            run += vals[q];
+        }
     }
-    int s = 0;
-#pragma unroll
-    for (int q = 0; q < SCAN_ITEMS; ++q) s += vals[q];
-    int total;
-    int run = block_exclusive_scan(s, sm, total) + tile_sums[blockIdx.x];
-    int outv[SCAN_ITEMS];
-#pragma unroll
-    for (int q = 0; q < SCAN_ITEMS; ++q) {
-        outv[q] = run;
-        run += vals[q];
-    }
-    if (full) {
-#pragma unroll
-        for (int q = 0; q < SCAN_ITEMS; q += 4)
-            *reinterpret_cast<int4 *>(data + b0 + q) = make_int4(outv[q], outv[q + 1], outv[q + 2], outv[q + 3]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < SCAN_ITEMS; ++q)
-            if (b0 + q < n) data[b0 + q] = outv[q];
+}
+
+// After the scatter: the counts and run counts of the list's keys back to 0,
+// so that both arrays are 0 at every key between sorts (they start so).
+__global__ void k_sort_clear(SortArgs a)
+{
+    const KeyDomain D = key_domain(a);
+    const long long n = D.cells + 1;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long g = domain_key(a, D, e);
+        a.counts[g] = 0;
+        a.runs[g] = 0;
     }
 }
 
@@ -1095,12 +1134,9 @@ int scan_tmp_size(long long n) { return (int)((n + SCAN_TILE - 1) / SCAN_TILE) +
 
 void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s)
 {
-    // counts of the ncell cells and of the lost-particle bucket: up to 2^31
-    // entries, so the element count is 64-bit; block counts fit in int
-    const long long ncount = (long long)a.ncell + 1;
+    // counts and runs are 0 at every key here (cleared at allocation and by
+    // the previous sort over the keys it used)
     const int nb = (int)(((long long)a.n + PBLOCK - 1) / PBLOCK);
-    launch_fill_i32(a.counts, 0, ncount, s);
-    launch_fill_i32(a.runs, 0, ncount, s);
     if (a.n > 0) {
         hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(PBLOCK), 0, s, a);
         hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(BOX_THREADS), 0, s, a, nb);
@@ -1108,13 +1144,14 @@ void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s)
         launch_fill_i32(a.box, INT_MAX, 3, s);
         launch_fill_i32(a.box + 3, INT_MIN, 3, s);
     }
-    const int ntiles = (int)((ncount + SCAN_TILE - 1) / SCAN_TILE);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(SCAN_THREADS), 0, s, a.counts, ncount, scan_tmp);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, s, scan_tmp, ntiles);
-    hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(SCAN_THREADS), 0, s, a.counts, ncount, scan_tmp);
-    if (a.n > 0) {
-        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(PBLOCK), 0, s, a);
-    }
+    // the list of keys has at most ncell + 1 entries
+    const long long tiles = ((long long)a.ncell + 1 + SCAN_TILE - 1) / SCAN_TILE;
+    const int grid = (int)std::min<long long>(tiles, SCAN_BLOCKS);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(grid), dim3(SCAN_THREADS), 0, s, a, scan_tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, s, a, scan_tmp);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(SCAN_THREADS), 0, s, a, scan_tmp);
+    if (a.n > 0) hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(PBLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_sort_clear, dim3(grid), dim3(SCAN_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_sort_done, dim3(1), dim3(64), 0, s, a);
 }
 

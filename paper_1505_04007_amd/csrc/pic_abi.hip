@@ -806,6 +806,9 @@ static pic_status init_impl(pic_ctx *c, const pic_grid *grid, double dx, double 
         TRY(dalloc(c, &c->counts, (size_t)ncell + 1));
         TRY(dalloc(c, &c->runs, (size_t)ncell + 1));
         TRY(dalloc(c, &c->first, (size_t)ncell + 1));
+        // 0 at every key from here on: each sort clears the keys it used
+        HIP_TRY(c, hipMemsetAsync(c->counts, 0, ((size_t)ncell + 1) * 4, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->runs, 0, ((size_t)ncell + 1) * 4, c->stream));
         TRY(dalloc(c, &c->box, 6));
         TRY(dalloc(c, &c->boxpart, 6 * (((size_t)c->np + pic::PBLOCK - 1) / pic::PBLOCK)));
         c->scan_len = pic::scan_tmp_size(ncell + 1);

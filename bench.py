@@ -335,7 +335,7 @@ def main():
     ap.add_argument("--deposit-mode", type=int, default=0)
     ap.add_argument("--field-sweep", type=int, default=0,
                     help="1: the one-pass E + H field sweep instead of the separate launches")
-    ap.add_argument("--timing-every", type=int, default=3,
+    ap.add_argument("--timing-every", type=int, default=7,
                     help="time the kernels of every this many steps with HIP events (every sort "
                          "too); 1 = every step.  Coprime to the sort interval, so the sample covers "
                          "every phase of it")

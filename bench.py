@@ -377,6 +377,9 @@ def main():
         bench_adjoint(args)
         return
     args.steps = 200 if args.steps is None else args.steps
+    if args.steps < args.timing_every:
+        # fewer steps than the interval might hold no sampled step at all
+        args.timing_every = 1
     w = workload(args.workload)
     torch.cuda.set_device(0)
     if args.sort_every is not None:
@@ -416,7 +419,7 @@ def main():
     per_step_push = pushes / args.steps
     algo = algorithmic_bytes(w, dom, per_step_push, st["pbox"])
     roof = None
-    if algo is not None:
+    if algo is not None and avg_s > 0:
         ach = algo / avg_s / 1e9
         rec = counters_for(dom, w.name)
         hbm = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

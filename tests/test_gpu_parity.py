@@ -247,6 +247,35 @@ def test_particles_leaving_the_box_are_dropped():
     _compare_fields(g, o, (nx, ny, nz), 1e-3)
 
 
+def test_sorts_after_the_whole_bunch_has_left():
+    """The bunch leaves through the +x wall (as in the oracle); the sorts that
+    follow see no live cell, only the bucket of lost particles, and every one
+    of them starts from counters that the previous sort cleared.  Pushes stop,
+    the particles stay lost, and the fields equal those of the same run without
+    sorts up to atomic-order round-off."""
+    nx, ny, nz, dx = 40, 24, 24, 4e-9
+    wpm, gm = pi.film_maps(nx, ny, nz, 6, 10)
+    rng = np.random.default_rng(pi.SEED0 + 43)
+    bunch = pi.gaussian_bunch(rng, 700, (35 * dx, 12 * dx, 13 * dx), (1.2 * dx,) * 3, 100e3)
+    w = pi.Workload("exit_all_x", nx, ny, nz, dx, pi.courant_dt(dx), (native.BC_CPML,) * 3, 6,
+                    wpm, gm, bunch, np.array([[20 * dx, 12 * dx, 10.5 * dx]]),
+                    pi.spectrum_omegas(nfreq=4), 72)
+    o = _oracle_of(w)
+    g = _gpu_of(w, sort_every=3)
+    ref = _gpu_of(w, sort_every=0)
+    o.step(60)  # the oracle's last particle leaves at step 49-54
+    g.step(60)
+    assert not o.particles()[6].any()
+    assert not np.isfinite(g.particles()[0]).any()
+    p0 = g.stats()["pushes"]
+    g.step(12)  # four more sorts over an empty live-cell box
+    ref.step(72)
+    assert g.stats()["pushes"] == p0 == ref.stats()["pushes"] and g.stats()["live"] == 0
+    assert not np.isfinite(g.particles()[0]).any()
+    for f in (native.FIELD_E, native.FIELD_H, native.FIELD_JPOL):
+        assert _rel(g.fields(f), ref.fields(f)) <= 1e-5, f
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_lanes_without_a_deposit_add_nothing(mode):
     """Regression: in the wavefront-reduced deposit a lane that does not deposit

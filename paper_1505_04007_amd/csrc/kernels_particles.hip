@@ -998,14 +998,19 @@ __device__ __forceinline__ KeyDomain key_domain(const SortArgs &a)
     return D;
 }
 
+// Element e of the list in 32-bit unsigned arithmetic: e < cells <= ncell
+// and every key below ncell fit, since ncell < 2^31 (a box exists, so its
+// widths are at least 1).
 __device__ __forceinline__ long long domain_key(const SortArgs &a, const KeyDomain &D, long long e)
 {
     if (e >= D.cells) return a.ncell;
-    const long long r = e / D.w[0];
-    const int x = (int)(e - r * D.w[0]);
-    const long long z = r / D.w[1];
-    const int y = (int)(r - z * D.w[1]);
-    return (long long)(D.lo[0] + x) + (long long)a.nx * ((D.lo[1] + y) + (long long)a.ny * (D.lo[2] + (int)z));
+    const unsigned ue = (unsigned)e, w0 = (unsigned)D.w[0], w1 = (unsigned)D.w[1];
+    const unsigned r = ue / w0;
+    const unsigned x = ue - r * w0;
+    const unsigned z = r / w1;
+    const unsigned y = r - z * w1;
+    return (long long)(((unsigned)D.lo[0] + x) +
+                       (unsigned)a.nx * (((unsigned)D.lo[1] + y) + (unsigned)a.ny * ((unsigned)D.lo[2] + z)));
 }
 
 // Workgroups of the scan launches: a fixed grid walking the list's tiles (the

@@ -849,12 +849,12 @@ __device__ __forceinline__ int cell_key(float x, float y, float z, int nx, int n
 // of a key that forms a single run.  The bunch is loaded ordered by x inside
 // each cell and drifts almost uniformly, so that order survives the sorts
 // and the particles of a wavefront stay ordered by their deposit windows.
-__global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
+__device__ __forceinline__ void count_body(const SortArgs &a, int blk)
 {
     __shared__ int bb[6];
     if (threadIdx.x < 6) bb[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
     __syncthreads();
-    const int p = blockIdx.x * PBLOCK + threadIdx.x;
+    const int p = blk * PBLOCK + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int pc = a.st->pcur;
     int key = a.ncell;
@@ -920,12 +920,14 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a)
     __syncthreads();
     // one partial box per workgroup (global atomics from every workgroup on
     // the same six words would serialise); k_box_reduce combines them
-    if (threadIdx.x < 6) a.boxpart[blockIdx.x * 6 + threadIdx.x] = bb[threadIdx.x];
+    if (threadIdx.x < 6) a.boxpart[blk * 6 + threadIdx.x] = bb[threadIdx.x];
 }
+
+__global__ __launch_bounds__(PBLOCK) void k_sort_count(SortArgs a) { count_body(a, blockIdx.x); }
 
 // The live-cell box from the count workgroups' partial boxes (one workgroup).
 constexpr int BOX_THREADS = 1024;
-__global__ __launch_bounds__(BOX_THREADS) void k_box_reduce(SortArgs a, int nparts)
+__device__ __forceinline__ void box_reduce_body(const SortArgs &a, int nparts)
 {
     __shared__ int red[6][BOX_THREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -950,6 +952,8 @@ __global__ __launch_bounds__(BOX_THREADS) void k_box_reduce(SortArgs a, int npar
         a.box[q] = r;
     }
 }
+
+__global__ __launch_bounds__(BOX_THREADS) void k_box_reduce(SortArgs a, int nparts) { box_reduce_body(a, nparts); }
 
 // Three-phase exclusive scan over SCAN_ITEMS * SCAN_THREADS elements per block.
 constexpr int SCAN_THREADS = 256;
@@ -1017,12 +1021,13 @@ __device__ __forceinline__ long long domain_key(const SortArgs &a, const KeyDoma
 // list's length is known on the device only).
 constexpr int SCAN_BLOCKS = 1024;
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(SortArgs a, int *tile_sums)
+// Workgroup blk of nblk walking the tiles.
+__device__ __forceinline__ void scan_tiles_body(const SortArgs &a, int *tile_sums, int blk, int nblk)
 {
     __shared__ int sm[SCAN_THREADS];
     const KeyDomain D = key_domain(a);
     const long long n = D.cells + 1;
-    for (long long b0 = (long long)blockIdx.x * SCAN_TILE; b0 < n; b0 += (long long)gridDim.x * SCAN_TILE) {
+    for (long long b0 = (long long)blk * SCAN_TILE; b0 < n; b0 += (long long)nblk * SCAN_TILE) {
         int s = 0;
         for (int q = 0; q < SCAN_ITEMS; ++q) {
             const long long e = b0 + (long long)q * SCAN_THREADS + threadIdx.x;
@@ -1034,9 +1039,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(SortArgs a, int *ti
     }
 }
 
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(SortArgs a, int *tile_sums)
+{
+    scan_tiles_body(a, tile_sums, blockIdx.x, gridDim.x);
+}
+
 // One workgroup; each thread scans SCAN_ITEMS consecutive tile sums of a
 // chunk serially around one block scan of the thread totals.
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(SortArgs a, int *tile_sums)
+__device__ __forceinline__ void scan_sums_body(const SortArgs &a, int *tile_sums)
 {
     __shared__ int sm[SCAN_THREADS];
     const int ntiles = (int)((key_domain(a).cells + 1 + SCAN_TILE - 1) / SCAN_TILE);
@@ -1061,12 +1071,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(SortArgs a, int *til
     }
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(SortArgs a, const int *tile_sums)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(SortArgs a, int *tile_sums) { scan_sums_body(a, tile_sums); }
+
+__device__ __forceinline__ void scan_apply_body(const SortArgs &a, const int *tile_sums, int blk, int nblk)
 {
     __shared__ int sm[SCAN_THREADS];
     const KeyDomain D = key_domain(a);
     const long long n = D.cells + 1;
-    for (long long t0 = (long long)blockIdx.x * SCAN_TILE; t0 < n; t0 += (long long)gridDim.x * SCAN_TILE) {
+    for (long long t0 = (long long)blk * SCAN_TILE; t0 < n; t0 += (long long)nblk * SCAN_TILE) {
         // each thread owns SCAN_ITEMS consecutive entries of the tile
         const long long b0 = t0 + (long long)threadIdx.x * SCAN_ITEMS;
         long long g[SCAN_ITEMS];
@@ -1089,22 +1101,29 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(SortArgs a, const i
     }
 }
 
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(SortArgs a, const int *tile_sums)
+{
+    scan_apply_body(a, tile_sums, blockIdx.x, gridDim.x);
+}
+
 // After the scatter: the counts and run counts of the list's keys back to 0,
 // so that both arrays are 0 at every key between sorts (they start so).
-__global__ void k_sort_clear(SortArgs a)
+__device__ __forceinline__ void sort_clear_body(const SortArgs &a, int blk, int nblk)
 {
     const KeyDomain D = key_domain(a);
     const long long n = D.cells + 1;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    for (long long e = (long long)blk * blockDim.x + threadIdx.x; e < n; e += (long long)nblk * blockDim.x) {
         const long long g = domain_key(a, D, e);
         a.counts[g] = 0;
         a.runs[g] = 0;
     }
 }
 
-__global__ __launch_bounds__(PBLOCK) void k_sort_scatter(SortArgs a)
+__global__ __launch_bounds__(SCAN_THREADS) void k_sort_clear(SortArgs a) { sort_clear_body(a, blockIdx.x, gridDim.x); }
+
+__device__ __forceinline__ void scatter_body(const SortArgs &a, int blk)
 {
-    const int p = blockIdx.x * PBLOCK + threadIdx.x;
+    const int p = blk * PBLOCK + threadIdx.x;
     if (p >= a.n) return;
     const int pc = a.st->pcur;
     // every load first, in two rounds (the particle, its key and rank; then
@@ -1124,15 +1143,75 @@ __global__ __launch_bounds__(PBLOCK) void k_sort_scatter(SortArgs a)
     a.id[pc ^ 1][dst] = id;
 }
 
+__global__ __launch_bounds__(PBLOCK) void k_sort_scatter(SortArgs a) { scatter_body(a, blockIdx.x); }
+
 // After the scatter: the sorted set becomes current and the sort clock restarts.
+__device__ __forceinline__ void done_body(const SortArgs &a)
+{
+    const int pc = a.st->pcur ^ 1;
+    a.st->pcur = pc;
+    a.st->since_sort = 0;
+    for (int c = 0; c < 6; ++c) a.st->P[c] = a.P[pc][c];
+}
+
 __global__ void k_sort_done(SortArgs a)
 {
-    if (threadIdx.x == 0) {
-        const int pc = a.st->pcur ^ 1;
-        a.st->pcur = pc;
-        a.st->since_sort = 0;
-        for (int c = 0; c < 6; ++c) a.st->P[c] = a.P[pc][c];
-    }
+    if (threadIdx.x == 0) done_body(a);
+}
+
+// ---- the sorts of many simulations in one launch per kernel ----
+// Particle workgroups come from a table (member << 24 | the workgroup's index
+// in that member, built by the host); each member's scans and clear get
+// SORT_BATCH_BLOCKS workgroups of their own, walking its key list; the
+// per-member single-workgroup kernels take one workgroup per member.
+constexpr int SORT_BATCH_BLOCKS = 64;
+
+__global__ __launch_bounds__(PBLOCK) void k_sort_count_batch(const SortArgs *__restrict__ args,
+                                                             const int *__restrict__ own)
+{
+    const int o = own[blockIdx.x];
+    count_body(args[o >> 24], o & 0xffffff);
+}
+
+__global__ __launch_bounds__(BOX_THREADS) void k_box_reduce_batch(const SortArgs *__restrict__ args)
+{
+    const SortArgs &a = args[blockIdx.x];
+    box_reduce_body(a, (int)(((long long)a.n + PBLOCK - 1) / PBLOCK));
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles_batch(const SortArgs *__restrict__ args)
+{
+    const SortArgs &a = args[blockIdx.x / SORT_BATCH_BLOCKS];
+    scan_tiles_body(a, a.scan_tmp, blockIdx.x % SORT_BATCH_BLOCKS, SORT_BATCH_BLOCKS);
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums_batch(const SortArgs *__restrict__ args)
+{
+    const SortArgs &a = args[blockIdx.x];
+    scan_sums_body(a, a.scan_tmp);
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply_batch(const SortArgs *__restrict__ args)
+{
+    const SortArgs &a = args[blockIdx.x / SORT_BATCH_BLOCKS];
+    scan_apply_body(a, a.scan_tmp, blockIdx.x % SORT_BATCH_BLOCKS, SORT_BATCH_BLOCKS);
+}
+
+__global__ __launch_bounds__(PBLOCK) void k_sort_scatter_batch(const SortArgs *__restrict__ args,
+                                                               const int *__restrict__ own)
+{
+    const int o = own[blockIdx.x];
+    scatter_body(args[o >> 24], o & 0xffffff);
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_sort_clear_batch(const SortArgs *__restrict__ args)
+{
+    sort_clear_body(args[blockIdx.x / SORT_BATCH_BLOCKS], blockIdx.x % SORT_BATCH_BLOCKS, SORT_BATCH_BLOCKS);
+}
+
+__global__ void k_sort_done_batch(const SortArgs *__restrict__ args, int nmem)
+{
+    if (threadIdx.x < nmem) done_body(args[threadIdx.x]);
 }
 
 int scan_tmp_size(long long n) { return (int)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
@@ -1158,6 +1237,21 @@ void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s)
     if (a.n > 0) hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(PBLOCK), 0, s, a);
     hipLaunchKernelGGL(k_sort_clear, dim3(grid), dim3(SCAN_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_sort_done, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch_sort_batch(const SortArgs *args, const int *own, int nown, int nmem, hipStream_t s)
+{
+    // every member has particles, and its counts and runs are 0 at every key
+    if (nmem <= 0 || nown <= 0) return;
+    const int g = nmem * SORT_BATCH_BLOCKS;
+    hipLaunchKernelGGL(k_sort_count_batch, dim3(nown), dim3(PBLOCK), 0, s, args, own);
+    hipLaunchKernelGGL(k_box_reduce_batch, dim3(nmem), dim3(BOX_THREADS), 0, s, args);
+    hipLaunchKernelGGL(k_scan_tiles_batch, dim3(g), dim3(SCAN_THREADS), 0, s, args);
+    hipLaunchKernelGGL(k_scan_sums_batch, dim3(nmem), dim3(SCAN_THREADS), 0, s, args);
+    hipLaunchKernelGGL(k_scan_apply_batch, dim3(g), dim3(SCAN_THREADS), 0, s, args);
+    hipLaunchKernelGGL(k_sort_scatter_batch, dim3(nown), dim3(PBLOCK), 0, s, args, own);
+    hipLaunchKernelGGL(k_sort_clear_batch, dim3(g), dim3(SCAN_THREADS), 0, s, args);
+    hipLaunchKernelGGL(k_sort_done_batch, dim3(1), dim3(64), 0, s, args, nmem);
 }
 
 }  // namespace pic

@@ -150,6 +150,7 @@ void build_args(pic_ctx *c)
     sa.first = c->first;
     sa.box = c->box;
     sa.boxpart = c->boxpart;
+    sa.scan_tmp = c->scan_tmp;
     sa.st = c->dstate;
 
     pic::ProbeArgs &pr = c->pr;

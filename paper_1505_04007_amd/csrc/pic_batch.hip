@@ -16,6 +16,9 @@ struct pic_batch {
     pic::PartArgs *d_pa = nullptr;
     pic::ProbeArgs *d_pr = nullptr;
     int *d_tiles = nullptr, *d_pblocks = nullptr;  // per work unit: member << 24 | its own unit
+    pic::SortArgs *d_sa = nullptr;                 // the sort arguments of the members with particles
+    int *d_sblocks = nullptr;                      // their sort workgroups (index into d_sa << 24 | unit)
+    int n_sorted = 0, total_sblocks = 0;
     size_t tiles_cap = 0;                          // entries d_tiles holds (the largest tile shape's count)
     int total_tiles = 0, total_pblocks = 0;
     int push_mode = 0;  // bit 0: per-lane atomics, bit 1: some member has a periodic x axis
@@ -57,7 +60,7 @@ void batch_free(pic_batch *b)
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->stream) (void)hipStreamDestroy(b->stream);
-    void *ptrs[5] = {b->d_fa, b->d_pa, b->d_pr, b->d_tiles, b->d_pblocks};
+    void *ptrs[7] = {b->d_fa, b->d_pa, b->d_pr, b->d_tiles, b->d_pblocks, b->d_sa, b->d_sblocks};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
@@ -143,9 +146,10 @@ pic_status batch_capture(pic_batch *b)
     BHIP(b, hipStreamSynchronize(b->stream));
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     for (int s2 = 0; s2 < b->graph_steps; ++s2) batch_launches(b);
+    // every member with particles is due at the end of the period: all their
+    // sorts in one launch per kernel
     if (b->particles && b->sort_every > 0)
-        for (pic_ctx *c : b->ctx)
-            if (c->np > 0) pic::launch_sort(c->sa, c->scan_tmp, b->stream);
+        pic::launch_sort_batch(b->d_sa, b->d_sblocks, b->total_sblocks, b->n_sorted, b->stream);
     hipError_t e = hipStreamEndCapture(b->stream, &b->graph);  // always leave capture mode
     if (e != hipSuccess) return bfail(b, PIC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
     BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
@@ -161,6 +165,8 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
     std::vector<pic::PartArgs> pa(n);
     std::vector<pic::ProbeArgs> pr(n);
     std::vector<long long> pblk(n, 0);
+    std::vector<pic::SortArgs> sa;
+    std::vector<long long> sblk;
     for (int q = 0; q < n; ++q) {
         pic_ctx *c = ctxs[q];
         if (!c || c->poisoned) return bfail(b, PIC_EINVAL, "context %d is NULL or poisoned", q);
@@ -182,11 +188,19 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
         pa[q] = c->pa;
         pr[q] = c->pr;
         pblk[q] = ((long long)c->np + pic::PUSH_BLOCK - 1) / pic::PUSH_BLOCK;
+        if (c->np > 0) {
+            sa.push_back(c->sa);
+            sblk.push_back(((long long)c->np + pic::PBLOCK - 1) / pic::PBLOCK);
+        }
     }
     long long total_pb = 0;
     for (long long v : pblk) total_pb += v;
     if (total_pb > INT_MAX) return bfail(b, PIC_EINVAL, "too many particles in the batch for one launch");
     const std::vector<int> ptab = unit_table(pblk);
+    long long total_sb = 0;
+    for (long long v : sblk) total_sb += v;
+    if (total_sb > INT_MAX) return bfail(b, PIC_EINVAL, "too many particles in the batch for one launch");
+    const std::vector<int> stab = unit_table(sblk);
     b->ext = ctxs[0]->stream;
     // an own stream: the members' stream may be the null stream, which cannot be captured
     BHIP(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
@@ -197,6 +211,10 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
     BHIP(b, hipMalloc(&b->d_pa, sizeof(pic::PartArgs) * n));
     BHIP(b, hipMalloc(&b->d_pr, sizeof(pic::ProbeArgs) * n));
     BHIP(b, hipMalloc(&b->d_pblocks, sizeof(int) * std::max<size_t>(ptab.size(), 1)));
+    b->n_sorted = (int)sa.size();
+    b->total_sblocks = (int)stab.size();
+    BHIP(b, hipMalloc(&b->d_sa, sizeof(pic::SortArgs) * std::max<size_t>(sa.size(), 1)));
+    BHIP(b, hipMalloc(&b->d_sblocks, sizeof(int) * std::max<size_t>(stab.size(), 1)));
     // the field tile table for the shape with the most tiles, so the tuner
     // rewrites it in place
     for (int v = 0; v < pic::N_TILE_SHAPES; ++v) {
@@ -212,6 +230,10 @@ static pic_status batch_create_impl(pic_batch *b, pic_ctx *const *ctxs, int32_t 
     BHIP(b, hipMemcpy(b->d_pr, pr.data(), sizeof(pic::ProbeArgs) * n, hipMemcpyHostToDevice));
     if (!ptab.empty())
         BHIP(b, hipMemcpy(b->d_pblocks, ptab.data(), sizeof(int) * ptab.size(), hipMemcpyHostToDevice));
+    if (!sa.empty()) {
+        BHIP(b, hipMemcpy(b->d_sa, sa.data(), sizeof(pic::SortArgs) * sa.size(), hipMemcpyHostToDevice));
+        BHIP(b, hipMemcpy(b->d_sblocks, stab.data(), sizeof(int) * stab.size(), hipMemcpyHostToDevice));
+    }
     b->use_graph = use_graph != 0;
     if (b->use_graph) return batch_capture(b);
     return PIC_OK;

@@ -170,6 +170,7 @@ struct SortArgs {
     int *first;   // [ncell + 1]
     int *box;     // [6] bounding box of live cells (lo x, y, z, hi x, y, z)
     int *boxpart; // [6 * count workgroups] each count workgroup's box, reduced into box
+    int *scan_tmp;  // [scan_tmp_size(ncell + 1)] the scans' tile sums
     DevState *st;
 };
 
@@ -287,6 +288,10 @@ void launch_push_deposit(const PartArgs &a, int mode, hipStream_t s);
 void launch_probe(const ProbeArgs &a, hipStream_t s);  // also advances the DevState
 void launch_fill_i32(int *p, int v, long long n, hipStream_t s);
 void launch_sort(const SortArgs &a, int *scan_tmp, hipStream_t s);
+// The sorts of nmem simulations (every one with particles) in one launch per
+// kernel: args[nmem] on the device, own[nown] the count and scatter
+// workgroups (member << 24 | workgroup index in that member).
+void launch_sort_batch(const SortArgs *args, const int *own, int nown, int nmem, hipStream_t s);
 int scan_tmp_size(long long n);
 
 // Batched forms: one launch over many simulations.  `args` is a device array

@@ -7,6 +7,7 @@ float atomics of the deposit make results order-dependent at round-off, so
 members are compared with their plain runs at 1e-5 and with the oracle at
 the 1e-3 particle tolerance.
 """
+import dataclasses
 import numpy as np
 import pytest
 
@@ -97,6 +98,33 @@ def test_batch_with_bunches_matches_plain_and_oracle():
     o.step(45)
     Eo = np.stack([o.E[c][: w.nx, : w.ny, : w.nz] for c in range(3)])
     assert _rel(sims[0].fields(native.FIELD_E), Eo) <= 1e-3
+    b.close()
+
+
+def test_batch_mixing_members_with_and_without_a_bunch():
+    """A member without particles takes no part in the batched sorts: a batch
+    of two bunches and one fields-only grid, replayed over four sort periods
+    and stepped on without the graph, matches its plain runs, the fields-only
+    member bit for bit."""
+    members = _members(True, sort_every=10)
+    w1, E1 = members[1]
+    members[1] = (dataclasses.replace(w1, bunch=None, sort_every=0), E1)
+    plain = _sims(members)
+    for s in plain:
+        s.step(45)
+    sims = _sims(members)
+    b = native.Batch(sims, use_graph=True)
+    b.step(45)
+    for q, (s, p) in enumerate(zip(sims, plain)):
+        if q == 1:
+            for which in (native.FIELD_E, native.FIELD_H, native.FIELD_JPOL):
+                assert np.array_equal(s.fields(which), p.fields(which))
+            assert s.stats()["pushes"] == 0
+        else:
+            assert _rel(s.fields(native.FIELD_E), p.fields(native.FIELD_E)) <= 1e-5
+            assert s.stats()["pushes"] == p.stats()["pushes"] > 0
+            Ps, Pp = s.particles(), p.particles()
+            assert np.abs(Ps[:3] - Pp[:3]).max() <= 1e-5 * w1.dx
     b.close()
 
 
